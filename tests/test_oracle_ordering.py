@@ -1,0 +1,180 @@
+"""Pins of the oracle's orderings (paper Section 3) against the paper and
+against properties the definitions fix."""
+import os
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import ordering as O
+
+
+def _figure_orders(golden_dir):
+    out = {}
+    with open(os.path.join(golden_dir, "hilbert_figure.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            out[int(parts[0])] = [tuple(int(v) for v in c.split(",")) for c in parts[1:]]
+    return out
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_hilbert_matches_paper_figure(golden_dir, p):
+    seq = _figure_orders(golden_dir)[p]
+    cells = [(x, y) for x in range(2 ** p) for y in range(2 ** p)]
+    got = sorted(cells, key=lambda c: O.hilbert_key_scalar(c[0], c[1], p))
+    assert got == seq
+
+
+def test_hilbert16_restricted_to_small_squares(golden_dir):
+    fig = _figure_orders(golden_dir)
+    cells4 = [(x, y) for x in range(4) for y in range(4)]
+    assert sorted(cells4, key=lambda c: O.hilbert_key_scalar(c[0], c[1], 16)) == fig[2]
+    cells8 = [(x, y) for x in range(8) for y in range(8)]
+    got = sorted(cells8, key=lambda c: O.hilbert_key_scalar(c[0], c[1], 16))
+    assert got == [(b, a) for (a, b) in fig[3]]  # orientation alternates with level parity
+
+
+@pytest.mark.parametrize("p", [4, 6])
+def test_hilbert_is_bijective_path_of_unit_steps(p):
+    side = 2 ** p
+    pos = {}
+    for x in range(side):
+        for y in range(side):
+            pos[O.hilbert_key_scalar(x, y, p)] = (x, y)
+    assert sorted(pos) == list(range(side * side))
+    for d in range(side * side - 1):
+        (x0, y0), (x1, y1) = pos[d], pos[d + 1]
+        assert abs(x0 - x1) + abs(y0 - y1) == 1
+    assert pos[0] == (0, 0)
+
+
+def test_morton_definition_small():
+    assert int(O.morton_key(1, 0)) == 1
+    assert int(O.morton_key(0, 1)) == 2
+    assert int(O.morton_key(1, 1)) == 3
+    assert int(O.morton_key(2, 0)) == 4
+    assert int(O.morton_key(65535, 65535)) == 2 ** 32 - 1
+    assert int(O.morton_key(65535, 0)) == 0x55555555
+
+
+def test_morton_bijective_8bit_and_z_shape():
+    xs, ys = np.meshgrid(np.arange(256), np.arange(256), indexing="ij")
+    keys = O.morton_key(xs.ravel(), ys.ravel(), bits=8)
+    assert np.array_equal(np.sort(keys), np.arange(256 * 256, dtype=np.uint64))
+    # the first four cells trace a "Z": (0,0) (1,0) (0,1) (1,1)
+    order = np.argsort(keys)[:4]
+    assert [(int(xs.ravel()[k]), int(ys.ravel()[k])) for k in order] == [(0, 0), (1, 0), (0, 1), (1, 1)]
+
+
+def test_quantize_rounding_and_clamp():
+    locs = np.array([[0.0, 1.0], [0.5, 0.25], [1.5 / 65535, 2.5 / 65535]])
+    q = O.quantize(locs)
+    assert q[0].tolist() == [0, 65535]
+    assert q[1].tolist() == [32768, 16384]  # 32767.5 -> 32768 (even); 16383.75 -> 16384
+    assert q[2].tolist() == [2, 2]          # ties to even: 1.5 -> 2, 2.5 -> 2
+    with pytest.raises(ValueError):
+        O.quantize(np.array([[0.1, 1.2]]))
+    with pytest.raises(ValueError):
+        O.quantize(np.array([[np.nan, 0.2]]))
+
+
+def test_sort_ties_by_original_index():
+    keys = np.array([5, 3, 5, 1, 3, 5], dtype=np.uint64)
+    assert O.sort_by_key(keys).tolist() == [3, 1, 4, 0, 2, 5]
+
+
+def test_forced_ties_curve_orders():
+    # points in the same quantisation cell keep their original order
+    locs = np.array([[0.5, 0.5], [0.2, 0.2], [0.5 + 1e-7, 0.5], [0.2, 0.2 + 1e-7]])
+    for kind in ("morton", "hilbert"):
+        perm = O.reorder(locs, kind)
+        assert perm.tolist() == [1, 3, 0, 2]
+
+
+def test_splitmix64_vectorised_formulation_agrees():
+    # a second, vectorised uint64 formulation of the same published recurrence
+    seed, count = 1234567, 257
+    with np.errstate(over="ignore"):
+        k = np.arange(1, count + 1, dtype=np.uint64)
+        z = np.uint64(seed) + k * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    assert np.array_equal(O.splitmix64_stream(seed, count), z)
+
+
+def test_random_order_is_bijection_and_seeded():
+    locs = synthetic.uniform_points(1000, 7)
+    a = O.reorder(locs, "random", seed=11)
+    b = O.reorder(locs, "random", seed=11)
+    c = O.reorder(locs, "random", seed=12)
+    assert np.array_equal(np.sort(a), np.arange(1000))
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_kdtree_collinear_is_identity():
+    t = np.linspace(0.05, 0.95, 37)
+    locs = np.stack([t, 0.5 * t + 0.1], axis=1)
+    assert O.reorder(locs, "kdtree").tolist() == list(range(37))
+
+
+def _kd_blocks(perm_locs, lo, hi, out, depth=0):
+    m = hi - lo
+    if m == 1:
+        out.append(depth)
+        return
+    left = (m + 1) // 2
+    _kd_blocks(perm_locs, lo, lo + left, out, depth + 1)
+    _kd_blocks(perm_locs, lo + left, hi, out, depth + 1)
+
+
+def test_kdtree_split_property_and_balance():
+    locs = synthetic.jittered_grid(13, 5)  # n = 169, odd sizes at many nodes
+    perm = O.reorder(locs, "kdtree")
+    assert np.array_equal(np.sort(perm), np.arange(169))
+    pl = locs[perm]
+
+    def check(lo, hi):
+        m = hi - lo
+        if m == 1:
+            return
+        pts = pl[lo:hi]
+        rx = np.ptp(pts[:, 0])
+        ry = np.ptp(pts[:, 1])
+        dim = 1 if ry > rx else 0
+        left = (m + 1) // 2
+        # every point of the left block is <= every point of the right block
+        assert pts[:left, dim].max() <= pts[left:, dim].min()
+        check(lo, lo + left)
+        check(lo + left, hi)
+
+    check(0, 169)
+    depths = []
+    _kd_blocks(pl, 0, 169, depths)
+    assert max(depths) - min(depths) <= 1
+
+
+def test_kdtree_brute_force_tiny():
+    # all permutations of 3 points on a skewed triangle: the order must not
+    # depend on the input order beyond the documented tie rule
+    base = np.array([[0.1, 0.3], [0.9, 0.35], [0.5, 0.9]])
+    ref = [tuple(base[k]) for k in O.reorder(base, "kdtree")]
+    for perm in ([1, 2, 0], [2, 0, 1], [2, 1, 0]):
+        locs = base[perm]
+        got = [tuple(locs[k]) for k in O.reorder(locs, "kdtree")]
+        assert got == ref
+    # x range 0.8 > y range 0.6: split on x; left = the 2 smallest x
+    assert ref[:2] in ([(0.1, 0.3), (0.5, 0.9)], [(0.5, 0.9), (0.1, 0.3)])
+
+
+def test_curve_orders_keep_neighbours_close():
+    locs = synthetic.jittered_grid(32, 3)
+    for kind in ("morton", "hilbert", "kdtree"):
+        p = locs[O.reorder(locs, kind)]
+        steps = np.linalg.norm(np.diff(p, axis=0), axis=1)
+        rnd = locs[O.reorder(locs, "random", seed=1)]
+        rsteps = np.linalg.norm(np.diff(rnd, axis=0), axis=1)
+        assert np.median(steps) < 0.25 * np.median(rsteps)
