@@ -1,0 +1,141 @@
+"""Throughput of l(theta) evaluations through the TLR path on one MI355X.
+
+Workload (default): n = 90,000 locations on a 300 x 300 jittered grid in the
+unit square, Matern nu = 1/2, beta = 0.1, sigma2 = 1, Hilbert ordering, tiles
+of nb = 900 (100 x 100 tiles), accuracy threshold tol = 1e-7.  One step is one
+full evaluation: covariance generation, per-tile compression, TLR Cholesky,
+forward solve, log-determinant and l, at parameters theta_true * exp(0.2 N(0,I))
+(seeded; a fresh theta every step, as an optimiser would propose).  Inputs
+(ordered locations, observations) are resident in HBM before timing starts.
+
+Prints one JSON line.  --config c1 runs the small 1,600-point case instead.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CONFIGS = {
+    # name: (grid m, nb, tol, theta_true, ordering, config number for seeds)
+    "c1": (40, 200, 1e-9, (1.0, 0.1, 0.5), "morton", 1),
+    "c3": (300, 900, 1e-7, (1.0, 0.1, 0.5), "hilbert", 3),
+}
+
+
+def cpu_baseline(locs_ordered: np.ndarray, z_ordered: np.ndarray, theta, n_full: int, sample_n: int):
+    """Dense oracle l on the first sample_n ordered points, scaled to n_full by n^3."""
+    import oracle.likelihood as OL
+
+    sub_l, sub_z = locs_ordered[:sample_n], z_ordered[:sample_n]
+    t0 = time.perf_counter()
+    OL.loglik_dense(sub_l, sub_z, theta)
+    dt = time.perf_counter() - t0
+    scale = (n_full / sample_n) ** 3
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {"value": 1.0 / (dt * scale), "unit": "evals/s", "cores": min(cores, threads), "kind": "oracle",
+            "sample": f"dense float64 oracle l (Matern matrix, LAPACK Cholesky, solve) on the first {sample_n} "
+                      f"ordered points: {dt:.2f} s; evals/s scaled to n={n_full} by (n/{sample_n})^3"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=10000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synthetic
+    from paper_2402_09356_amd import binding as B
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    m, nb, tol, theta_true, kind, cfg = CONFIGS[args.config]
+    n = m * m
+    locs = synthetic.jittered_grid(m, synthetic.seed_for(cfg, synthetic.SEED_LOCS))
+    # white-noise observations: the work of an evaluation does not depend on Z
+    z = synthetic.standard_normal(n, synthetic.seed_for(cfg, synthetic.SEED_Z))
+    thetas = synthetic.theta_perturbations(theta_true, args.warmup + args.steps,
+                                           synthetic.seed_for(cfg, synthetic.SEED_THETA))
+
+    dlocs = torch.from_numpy(locs).to(dev)
+    perm = B.reorder(dlocs, kind, synthetic.seed_for(cfg, synthetic.SEED_ORDER))
+    olocs, oz = B.apply_perm(perm, dlocs, torch.from_numpy(z).to(dev))
+    plan = B.Plan(n, nb, precision=args.precision)
+    ws = plan.workspace(dev)
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    print(f"# workspace {plan.ws_bytes / 2**30:.2f} GiB, nt={plan.nt}, maxrank={plan.maxrank}", file=sys.stderr,
+          flush=True)
+    for w in range(args.warmup):
+        plan.loglik(ws, olocs, oz, thetas[w], tol, out=out)
+        torch.cuda.synchronize()
+        print(f"# warmup {w}: l={out[2].item():.6f}", file=sys.stderr, flush=True)
+    lat = []
+    lls = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        t0 = time.perf_counter()
+        plan.loglik(ws, olocs, oz, thetas[args.warmup + k], tol, out=out)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        lls.append(out[2].item())
+        print(f"# step {k}: {lat[-1] * 1e3:.1f} ms l={lls[-1]:.6f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    st = plan.status(ws)
+    lat_ms = np.asarray(lat) * 1e3
+    rec = {
+        "metric": "l(theta) evals/s, n=90k TLR Matern",
+        "value": args.steps / total,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: n={n} jittered grid, nu=0.5 beta=0.1 sigma2=1, {kind} order, "
+                               f"nb={nb}, tol={tol:g}, theta=theta_true*exp(0.2 N(0,I)) per step",
+                   "n": n, "nb": nb, "tol": tol, "ordering": kind, "precision": args.precision},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "max_rank": st["max_rank"],
+        "rank_sum": st["rank_sum"],
+        "all_finite": bool(np.all(np.isfinite(lls))),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        ol = olocs.cpu().numpy()
+        ozz = oz.cpu().numpy()
+        rec["cpu_baseline"] = cpu_baseline(ol, ozz, theta_true, n, min(args.cpu_sample, n))
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

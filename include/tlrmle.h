@@ -1,0 +1,237 @@
+/*
+ * tlrmle.h -- C ABI of the MI355X tile-low-rank Matern log-likelihood library.
+ *
+ * The library evaluates the Gaussian log-likelihood
+ *     l(theta) = -(n/2) log(2 pi) - (1/2) log|Sigma(theta)| - (1/2) Z^T Sigma(theta)^-1 Z
+ * (paper Section 1, eq. "loglik") for the Matern covariance of Section 4.1
+ * (eq. "maternkernel"), theta = (sigma2, beta, nu), after the locations have
+ * been reordered (Section 3), through a tile low-rank (TLR) Cholesky
+ * factorisation of Sigma (Section 2).
+ *
+ * Conventions shared by every call:
+ *  - Pointers named d_* are device (HBM) pointers owned by the caller; h_*
+ *    are host pointers owned by the caller.  The library never keeps a
+ *    reference to them after the call returns (except d_ws between calls of
+ *    one evaluation, see below).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call that takes a stream is asynchronous on it unless stated.
+ *  - Argument errors are detected on the host before any launch and returned
+ *    as TLR_E_* codes; nothing is enqueued in that case.  Numerical failures
+ *    (a non-positive pivot, a tile rank above the cap) are written by the
+ *    kernels to a status word inside the workspace (first failure wins) and
+ *    surface as l = -infinity; read them with tlr_status_read().
+ *  - Layouts: locations are n x 2 float64, array-of-structs (x0, y0, x1, ...);
+ *    matrices are column-major.
+ *  - No global mutable state: calls on different workspaces may run
+ *    concurrently from different host threads.
+ */
+#ifndef TLRMLE_H
+#define TLRMLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tlr_status;
+
+enum {
+    TLR_OK = 0,
+    TLR_E_INVAL = 1,        /* bad argument (null pointer, size, theta <= 0, NaN) */
+    TLR_E_NOMEM = 2,        /* workspace smaller than the queried size */
+    TLR_E_UNSUPPORTED = 3,  /* combination not implemented */
+    TLR_E_HIP = 4,          /* a HIP runtime call failed */
+    TLR_NOT_SPD = 16,       /* device: non-positive pivot in a diagonal tile */
+    TLR_RANK_OVERFLOW = 17, /* device: a tile rank exceeded the plan's rank cap */
+    TLR_E_DOMAIN = 18       /* device: a location outside [0,1]^2 or not finite */
+};
+
+/* Orderings of paper Section 3: NONE = generation order ("No Order"),
+ * RANDOM = seeded permutation, MORTON / HILBERT = space-filling-curve keys of
+ * the 16-bit encoded coordinates (Sections 3.1.1, 3.1.2), KDTREE = in-order
+ * leaves of the median-split KD-tree (Section 3.2). */
+typedef enum {
+    TLR_ORDER_NONE = 0,
+    TLR_ORDER_RANDOM = 1,
+    TLR_ORDER_MORTON = 2,
+    TLR_ORDER_HILBERT = 3,
+    TLR_ORDER_KDTREE = 4
+} tlr_ordering;
+
+/* Arithmetic of the factorisation.  FP64 everywhere, or low-rank factors and
+ * off-diagonal products in FP32 (diagonal-tile Cholesky, log-determinant and
+ * quadratic-form reductions stay FP64). */
+typedef enum {
+    TLR_FP64 = 0,
+    TLR_MIXED_FP32 = 1
+} tlr_precision;
+
+/* Matern parameters (paper eq. "maternkernel"): variance, range, smoothness. */
+typedef struct {
+    double sigma2;
+    double beta;
+    double nu;
+} tlr_theta;
+
+/* Device status, read back by tlr_status_read(). */
+typedef struct {
+    int32_t code;       /* TLR_OK or the first TLR_NOT_SPD / TLR_RANK_OVERFLOW */
+    int32_t tile_i;     /* tile row of the first failure (-1 if none) */
+    int32_t tile_j;     /* tile column of the first failure (-1 if none) */
+    int32_t max_rank;   /* largest off-diagonal rank held by the factor */
+    int64_t rank_sum;   /* sum of off-diagonal ranks held by the factor */
+} tlr_devinfo;
+
+/* flags for tlr_reorder */
+#define TLR_REORDER_DEQUANTIZE 1u /* also write code/65535 coordinates (decoding step) */
+
+/* flags for tlr_plan_create */
+#define TLR_PLAN_DEFAULT 0u
+
+typedef struct tlr_plan_s *tlr_plan;
+
+/* ------------------------------------------------------------------------ */
+/* Ordering (paper Section 3)                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Device workspace bytes tlr_reorder needs for n points of the given kind. */
+size_t tlr_reorder_ws_bytes(int64_t n, tlr_ordering kind);
+
+/* Ordering permutation.
+ * d_locs: n x 2 float64 AoS, every coordinate in [0,1] (Section 3.1's unit
+ *         square); outside values set TLR_E_DOMAIN in the returned status
+ *         after a synchronous check (this call synchronises `stream` once).
+ * kind:   see tlr_ordering.  MORTON/HILBERT encode each coordinate as
+ *         rint(x * 65535) (ties to even) -- the "Encoding" step -- build the
+ *         32-bit curve key and sort by (key, original index) -- the "Sorting"
+ *         step.  RANDOM sorts by the SplitMix64 stream started at `seed`.
+ *         KDTREE splits on the larger-range coordinate at the median, first
+ *         ceil(m/2) points (by coordinate, then index) to the left.
+ * d_perm: out, n int32: d_perm[k] = original index of the k-th ordered point.
+ * d_ws:   caller workspace of at least tlr_reorder_ws_bytes(n, kind) bytes.
+ * The result is bit-identical to the paper-derived CPU definition. */
+tlr_status tlr_reorder(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed,
+                       uint32_t flags, int32_t *d_perm, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Gather locations (n x 2 AoS) and observations by d_perm:
+ * d_locs_out[k] = d_locs[d_perm[k]], d_z_out[k] = d_z[d_perm[k]].
+ * With dequantize != 0 the gathered coordinates are rint(x*65535)/65535
+ * (the "Decoding" step of Section 3.1).  d_z / d_z_out may be NULL. */
+tlr_status tlr_apply_perm(const int32_t *d_perm, int64_t n, const double *d_locs, const double *d_z,
+                          double *d_locs_out, double *d_z_out, int32_t dequantize, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Plan and workspace                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Host-only, immutable description of one problem shape.
+ * n >= 1 points, tile size nb >= 16 (nt = ceil(n/nb) tiles per side; a
+ * ragged last tile is padded with identity rows/columns and zero
+ * observations, which leaves log|Sigma| and the quadratic form unchanged).
+ * maxrank: cap on an off-diagonal tile rank; <= 0 means nb/2 (the storage
+ * break-even of Section 3).  A tile whose rank exceeds the cap stops the
+ * factorisation with TLR_RANK_OVERFLOW (the "cannot proceed" case of
+ * Section 3.3 / Table "memory").
+ * Allocates host memory only. */
+tlr_status tlr_plan_create(tlr_plan *out, int64_t n, int32_t nb, int32_t maxrank,
+                           tlr_precision precision, uint32_t flags);
+void tlr_plan_destroy(tlr_plan plan);
+
+/* Bytes of device workspace one evaluation needs (diagonal tiles, low-rank
+ * factor slots of 2*nb*maxrank words per off-diagonal tile, sketch buffers,
+ * status word).  The caller allocates it; the library never allocates device
+ * memory on the evaluation path. */
+size_t tlr_plan_ws_bytes(tlr_plan plan);
+
+/* Tile geometry of the plan (any pointer may be NULL). */
+void tlr_plan_shape(tlr_plan plan, int64_t *n, int32_t *nb, int32_t *nt, int32_t *maxrank);
+
+/* ------------------------------------------------------------------------ */
+/* The hot path, step by step (an evaluation is gen -> compress -> potrf ->  */
+/* solve_logdet on one workspace; tlr_loglik runs all four)                  */
+/* ------------------------------------------------------------------------ */
+
+/* Covariance generation (eqs. "covfunc", "maternkernel"):
+ * diagonal tiles Sigma_kk written densely into the workspace, and the
+ * locations + theta recorded for the off-diagonal tiles, which are generated
+ * on demand by tlr_compress.  d_locs: ordered n x 2 AoS.  Resets the device
+ * status word. */
+tlr_status tlr_gen_tiles(tlr_plan plan, const double *d_locs, tlr_theta theta, void *d_ws,
+                         size_t ws_bytes, void *stream);
+
+/* Compression (Section 2, Fig. "tlr"; Section 3's accuracy threshold):
+ * every off-diagonal tile A_ij (i > j) becomes U_ij V_ij^T with
+ * rank r_ij = #{singular values > tol} (absolute threshold), estimated by a
+ * randomised range finder with one power step and an exact SVD of the small
+ * projected matrix.  d_ranks: optional out, nt*nt int32 (row-major, entry
+ * i*nt + j for i > j; other entries 0): the rank of each tile, or -1 when it
+ * exceeded maxrank (then the status word is TLR_RANK_OVERFLOW). */
+tlr_status tlr_compress(tlr_plan plan, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks,
+                        void *stream);
+
+/* TLR Cholesky factorisation Sigma~ = L L^T, in place in the workspace.
+ * Left-looking by tile column: the Schur complement of each off-diagonal
+ * tile is re-compressed once at the plan's tol; diagonal tiles are factored
+ * densely in FP64.  A non-positive pivot sets TLR_NOT_SPD (tile k, k).
+ * Host-synchronises `stream` once per tile column (ranks are read back to
+ * size the next column's work). */
+tlr_status tlr_potrf(tlr_plan plan, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Forward solve y = L^-1 Z, log|Sigma~| = 2 sum log L_ii, quad = y^T y, in
+ * FP64.  d_z: ordered observations, n float64.  d_out: out, 3 float64 on the
+ * device: {logdet, quad, loglik}; loglik = -inf when the status is not OK. */
+tlr_status tlr_solve_logdet(tlr_plan plan, const double *d_z, void *d_ws, size_t ws_bytes,
+                            double *d_out, void *stream);
+
+/* One evaluation: gen_tiles -> compress -> potrf -> solve_logdet.
+ * d_out as for tlr_solve_logdet.  d_ranks as for tlr_compress (may be NULL). */
+tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tlr_theta theta,
+                      double tol, void *d_ws, size_t ws_bytes, double *d_out, int32_t *d_ranks,
+                      void *stream);
+
+/* Synchronises `stream`, then reads the device status word. */
+tlr_status tlr_status_read(tlr_plan plan, const void *d_ws, tlr_devinfo *out, void *stream);
+
+/* Human-readable name of a status code (static string). */
+const char *tlr_strerror(tlr_status code);
+
+/* Version string of the library build. */
+const char *tlr_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel diagnostics (used by the test suite to check the building blocks)  */
+/* ------------------------------------------------------------------------ */
+
+/* C = alpha op(A) op(B) + beta C on the float64 matrix-core GEMM used by
+ * every sketch product and update above.  Column-major device matrices;
+ * op(X) = X^T when trans_x != 0.  op(A) is M x K, op(B) is K x N.  With
+ * beta == 0, C is not read.  Synchronises `stream`; allocates and frees a
+ * one-descriptor device temporary (diagnostic use only). */
+tlr_status tlr_diag_gemm(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K, double alpha,
+                         const double *d_A, int32_t lda, const double *d_B, int32_t ldb, double beta,
+                         double *d_C, int32_t ldc, void *stream);
+
+/* Copy tile (i, j) of the matrix held in the workspace into d_out (nb x nb,
+ * column-major): for i == j the dense diagonal tile (Sigma_jj after
+ * tlr_gen_tiles, its Cholesky factor in the lower triangle after tlr_potrf);
+ * for i > j the product U_ij V_ij^T of the stored low-rank factors (the
+ * compressed Sigma_ij after tlr_compress, L_ij after tlr_potrf).  *h_rank
+ * (may be NULL) receives the tile's rank (nb for a diagonal tile).
+ * Synchronises `stream`. */
+tlr_status tlr_diag_tile(tlr_plan plan, const void *d_ws, int32_t i, int32_t j, double *d_out, int32_t *h_rank,
+                         void *stream);
+
+/* Singular values (descending) and left singular vectors of k x k matrices
+ * by the one-sided Jacobi kernel of the compression step.  d_A: count
+ * matrices, each k x k column-major, consecutive; d_S: count x k; d_X:
+ * count x k x k.  d_rank: count int32, #{s > tol}.  k <= 512. */
+tlr_status tlr_diag_svd(int32_t count, int32_t k, const double *d_A, double tol, double *d_S, double *d_X,
+                        int32_t *d_rank, void *d_scratch, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLRMLE_H */

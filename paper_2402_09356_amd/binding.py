@@ -1,0 +1,219 @@
+"""ctypes binding of include/tlrmle.h (argument marshalling only).
+
+Tensors must be CUDA (HIP) tensors of the documented dtype and shape; the
+binding passes their data pointers and the current stream to the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtlrmle.so")
+
+ORDERINGS = {"none": 0, "random": 1, "morton": 2, "hilbert": 3, "kdtree": 4}
+PRECISIONS = {"fp64": 0, "mixed_fp32": 1}
+STATUS = {0: "TLR_OK", 1: "TLR_E_INVAL", 2: "TLR_E_NOMEM", 3: "TLR_E_UNSUPPORTED", 4: "TLR_E_HIP",
+          16: "TLR_NOT_SPD", 17: "TLR_RANK_OVERFLOW", 18: "TLR_E_DOMAIN"}
+
+
+class TlrError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+def status_name(code: int) -> str:
+    return STATUS.get(code, str(code))
+
+
+class _Theta(ctypes.Structure):
+    _fields_ = [("sigma2", ctypes.c_double), ("beta", ctypes.c_double), ("nu", ctypes.c_double)]
+
+
+class DevInfo(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("tile_i", ctypes.c_int32), ("tile_j", ctypes.c_int32),
+                ("max_rank", ctypes.c_int32), ("rank_sum", ctypes.c_int64)]
+
+
+_lib = None
+
+P = ctypes.c_void_p
+I32, I64, U32, U64, F64, SZ = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64,
+                               ctypes.c_double, ctypes.c_size_t)
+
+_SIGNATURES = {
+    "tlr_reorder_ws_bytes": (SZ, [I64, I32]),
+    "tlr_reorder": (I32, [P, I64, I32, U64, U32, P, P, SZ, P]),
+    "tlr_apply_perm": (I32, [P, I64, P, P, P, P, I32, P]),
+    "tlr_plan_create": (I32, [ctypes.POINTER(P), I64, I32, I32, I32, U32]),
+    "tlr_plan_destroy": (None, [P]),
+    "tlr_plan_ws_bytes": (SZ, [P]),
+    "tlr_plan_shape": (None, [P, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                              ctypes.POINTER(I32)]),
+    "tlr_gen_tiles": (I32, [P, P, _Theta, P, SZ, P]),
+    "tlr_compress": (I32, [P, F64, P, SZ, P, P]),
+    "tlr_potrf": (I32, [P, P, SZ, P]),
+    "tlr_solve_logdet": (I32, [P, P, P, SZ, P, P]),
+    "tlr_loglik": (I32, [P, P, P, _Theta, F64, P, SZ, P, P, P]),
+    "tlr_status_read": (I32, [P, P, ctypes.POINTER(DevInfo), P]),
+    "tlr_strerror": (ctypes.c_char_p, [I32]),
+    "tlr_version": (ctypes.c_char_p, []),
+    "tlr_diag_gemm": (I32, [I32, I32, I32, I32, I32, F64, P, I32, P, I32, F64, P, I32, P]),
+    "tlr_diag_svd": (I32, [I32, I32, P, F64, P, P, P, P, P]),
+    "tlr_diag_tile": (I32, [P, P, I32, I32, P, ctypes.POINTER(I32), P]),
+}
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_09356_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(code, what):
+    if code != 0:
+        raise TlrError(code, what)
+
+
+def reorder(locs: torch.Tensor, kind: str, seed: int = 0) -> torch.Tensor:
+    """Ordering permutation of n x 2 float64 device locations (int32, device)."""
+    if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
+        raise ValueError("locs must be an n x 2 float64 tensor")
+    n = locs.shape[0]
+    k = ORDERINGS[kind]
+    L = lib()
+    ws_bytes = L.tlr_reorder_ws_bytes(n, k)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=locs.device)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=locs.device)[:n]
+    _check(L.tlr_reorder(_ptr(locs), n, k, seed & (2 ** 64 - 1), 0, _ptr(perm), _ptr(ws), ws_bytes, _stream()),
+           "tlr_reorder")
+    return perm
+
+
+def apply_perm(perm: torch.Tensor, locs: torch.Tensor, z: torch.Tensor | None = None, dequantize: bool = False):
+    n = locs.shape[0]
+    locs_out = torch.empty_like(locs)
+    z_out = torch.empty_like(z) if z is not None else None
+    _check(lib().tlr_apply_perm(_ptr(perm), n, _ptr(locs), _ptr(z), _ptr(locs_out), _ptr(z_out), int(dequantize),
+                                _stream()), "tlr_apply_perm")
+    return locs_out, z_out
+
+
+class Plan:
+    """Owns a tlr_plan handle; workspaces are torch uint8 device tensors."""
+
+    def __init__(self, n: int, nb: int, maxrank: int = 0, precision: str = "fp64"):
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.tlr_plan_create(ctypes.byref(h), n, nb, maxrank, PRECISIONS[precision], 0), "tlr_plan_create")
+        self._h = h
+        self.n = n
+        self.nb = nb
+        n_, nb_, nt_, mr_ = I64(), I32(), I32(), I32()
+        L.tlr_plan_shape(h, ctypes.byref(n_), ctypes.byref(nb_), ctypes.byref(nt_), ctypes.byref(mr_))
+        self.nt = nt_.value
+        self.maxrank = mr_.value
+        self.ws_bytes = L.tlr_plan_ws_bytes(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tlr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def gen_tiles(self, ws, locs, theta):
+        _check(lib().tlr_gen_tiles(self._h, _ptr(locs), _Theta(*map(float, theta)), _ptr(ws), ws.numel(),
+                                   _stream()), "tlr_gen_tiles")
+
+    def compress(self, ws, tol, ranks: torch.Tensor | None = None):
+        _check(lib().tlr_compress(self._h, float(tol), _ptr(ws), ws.numel(), _ptr(ranks), _stream()),
+               "tlr_compress")
+
+    def potrf(self, ws):
+        _check(lib().tlr_potrf(self._h, _ptr(ws), ws.numel(), _stream()), "tlr_potrf")
+
+    def solve_logdet(self, ws, z, out=None):
+        out = torch.empty(3, dtype=torch.float64, device=z.device) if out is None else out
+        _check(lib().tlr_solve_logdet(self._h, _ptr(z), _ptr(ws), ws.numel(), _ptr(out), _stream()),
+               "tlr_solve_logdet")
+        return out
+
+    def loglik(self, ws, locs, z, theta, tol, out=None, ranks=None):
+        out = torch.empty(3, dtype=torch.float64, device=z.device) if out is None else out
+        _check(lib().tlr_loglik(self._h, _ptr(locs), _ptr(z), _Theta(*map(float, theta)), float(tol), _ptr(ws),
+                                ws.numel(), _ptr(out), _ptr(ranks), _stream()), "tlr_loglik")
+        return out
+
+    def tile(self, ws, i, j):
+        """(nb x nb numpy array of tile (i, j) in row-major math layout, rank)."""
+        out = torch.empty(self.nb, self.nb, dtype=torch.float64, device=ws.device)
+        r = I32()
+        _check(lib().tlr_diag_tile(self._h, _ptr(ws), i, j, _ptr(out), ctypes.byref(r), _stream()),
+               "tlr_diag_tile")
+        return out.t().cpu().numpy(), r.value
+
+    def status(self, ws) -> dict:
+        info = DevInfo()
+        _check(lib().tlr_status_read(self._h, _ptr(ws), ctypes.byref(info), _stream()), "tlr_status_read")
+        return {"code": info.code, "name": status_name(info.code), "tile": (info.tile_i, info.tile_j),
+                "max_rank": info.max_rank, "rank_sum": info.rank_sum}
+
+
+def diag_gemm(a, b, c, alpha=1.0, beta=0.0, trans_a=False, trans_b=False):
+    """c = alpha op(a) op(b) + beta c with column-major views of row-major torch tensors.
+
+    Column-major M x K data is a row-major K x M tensor; callers pass
+    tensors holding the transposes (``t().contiguous()``)."""
+    M = c.shape[1]
+    N = c.shape[0]
+    K = a.shape[0] if not trans_a else a.shape[1]
+    lda, ldb, ldc = a.shape[1], b.shape[1], c.shape[1]
+    _check(lib().tlr_diag_gemm(int(trans_a), int(trans_b), M, N, K, float(alpha), _ptr(a), lda, _ptr(b), ldb,
+                               float(beta), _ptr(c), ldc, _stream()), "tlr_diag_gemm")
+    return c
+
+
+def diag_svd(mats: torch.Tensor, tol: float):
+    """mats: count x k x k (each stored column-major, i.e. the tensor holds A^T)."""
+    count, k, _ = mats.shape
+    S = torch.empty(count, k, dtype=torch.float64, device=mats.device)
+    X = torch.empty(count, k, k, dtype=torch.float64, device=mats.device)
+    rank = torch.empty(count, dtype=torch.int32, device=mats.device)
+    scratch = torch.empty(512 + count * (8 * k * k + 144), dtype=torch.uint8, device=mats.device)
+    _check(lib().tlr_diag_svd(count, k, _ptr(mats), float(tol), _ptr(S), _ptr(X), _ptr(rank), _ptr(scratch),
+                              _stream()), "tlr_diag_svd")
+    return S, X, rank

@@ -1,0 +1,182 @@
+// extern "C" entry points declared in include/tlrmle.h.
+#include "kernels.h"
+
+namespace tlr {
+tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precision prec, uint32_t flags);
+void plan_destroy(tlr_plan p);
+size_t plan_ws_bytes(tlr_plan p);
+tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws, size_t ws_bytes, hipStream_t s);
+tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks, hipStream_t s);
+tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s);
+tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_bytes, double *d_out, hipStream_t s);
+tlr_status status_read(tlr_plan p, const void *d_ws, tlr_devinfo *out, hipStream_t s);
+void plan_shape(tlr_plan p, int64_t *n, int32_t *nb, int32_t *nt, int32_t *maxrank);
+tlr_status tile_read(tlr_plan p, const void *d_ws, int i, int j, double *d_out, int32_t *h_rank, hipStream_t s);
+}  // namespace tlr
+
+static inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+extern "C" {
+
+size_t tlr_reorder_ws_bytes(int64_t n, tlr_ordering kind) { return tlr::reorder_ws_bytes(n, kind); }
+
+tlr_status tlr_reorder(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed, uint32_t flags,
+                       int32_t *d_perm, void *d_ws, size_t ws_bytes, void *stream) {
+    return tlr::reorder(d_locs, n, kind, seed, flags, d_perm, d_ws, ws_bytes, as_stream(stream));
+}
+
+tlr_status tlr_apply_perm(const int32_t *d_perm, int64_t n, const double *d_locs, const double *d_z,
+                          double *d_locs_out, double *d_z_out, int32_t dequantize, void *stream) {
+    return tlr::apply_perm(d_perm, n, d_locs, d_z, d_locs_out, d_z_out, dequantize, as_stream(stream));
+}
+
+tlr_status tlr_plan_create(tlr_plan *out, int64_t n, int32_t nb, int32_t maxrank, tlr_precision precision,
+                           uint32_t flags) {
+    return tlr::plan_create(out, n, nb, maxrank, precision, flags);
+}
+
+void tlr_plan_destroy(tlr_plan plan) { tlr::plan_destroy(plan); }
+
+size_t tlr_plan_ws_bytes(tlr_plan plan) { return tlr::plan_ws_bytes(plan); }
+
+void tlr_plan_shape(tlr_plan plan, int64_t *n, int32_t *nb, int32_t *nt, int32_t *maxrank) {
+    tlr::plan_shape(plan, n, nb, nt, maxrank);
+}
+
+tlr_status tlr_gen_tiles(tlr_plan plan, const double *d_locs, tlr_theta theta, void *d_ws, size_t ws_bytes,
+                         void *stream) {
+    return tlr::gen_tiles(plan, d_locs, theta, d_ws, ws_bytes, as_stream(stream));
+}
+
+tlr_status tlr_compress(tlr_plan plan, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks, void *stream) {
+    return tlr::compress(plan, tol, d_ws, ws_bytes, d_ranks, as_stream(stream));
+}
+
+tlr_status tlr_potrf(tlr_plan plan, void *d_ws, size_t ws_bytes, void *stream) {
+    return tlr::potrf(plan, d_ws, ws_bytes, as_stream(stream));
+}
+
+tlr_status tlr_solve_logdet(tlr_plan plan, const double *d_z, void *d_ws, size_t ws_bytes, double *d_out,
+                            void *stream) {
+    return tlr::solve_logdet(plan, d_z, d_ws, ws_bytes, d_out, as_stream(stream));
+}
+
+tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tlr_theta theta, double tol,
+                      void *d_ws, size_t ws_bytes, double *d_out, int32_t *d_ranks, void *stream) {
+    hipStream_t s = as_stream(stream);
+    if (!plan || !d_locs || !d_z || !d_ws || !d_out) return TLR_E_INVAL;
+    tlr_status st = tlr::gen_tiles(plan, d_locs, theta, d_ws, ws_bytes, s);
+    if (st != TLR_OK) return st;
+    st = tlr::compress(plan, tol, d_ws, ws_bytes, d_ranks, s);
+    if (st != TLR_OK) return st;
+    st = tlr::potrf(plan, d_ws, ws_bytes, s);
+    if (st != TLR_OK) return st;
+    return tlr::solve_logdet(plan, d_z, d_ws, ws_bytes, d_out, s);
+}
+
+tlr_status tlr_status_read(tlr_plan plan, const void *d_ws, tlr_devinfo *out, void *stream) {
+    return tlr::status_read(plan, d_ws, out, as_stream(stream));
+}
+
+const char *tlr_strerror(tlr_status code) {
+    switch (code) {
+        case TLR_OK: return "ok";
+        case TLR_E_INVAL: return "invalid argument";
+        case TLR_E_NOMEM: return "workspace too small";
+        case TLR_E_UNSUPPORTED: return "unsupported";
+        case TLR_E_HIP: return "HIP runtime error";
+        case TLR_NOT_SPD: return "matrix not positive definite";
+        case TLR_RANK_OVERFLOW: return "tile rank above the rank cap";
+        case TLR_E_DOMAIN: return "location outside the unit square";
+        default: return "unknown status";
+    }
+}
+
+const char *tlr_version(void) { return "tlrmle 0.1 (gfx950)"; }
+
+tlr_status tlr_diag_tile(tlr_plan plan, const void *d_ws, int32_t i, int32_t j, double *d_out, int32_t *h_rank,
+                         void *stream) {
+    return tlr::tile_read(plan, d_ws, i, j, d_out, h_rank, as_stream(stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------- diagnostics --
+#include <vector>
+
+static_assert(sizeof(tlr::SmallDesc) <= 128, "diag_svd scratch formula assumes <= 128-byte descriptors");
+
+extern "C" tlr_status tlr_diag_gemm(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K, double alpha,
+                                    const double *d_A, int32_t lda, const double *d_B, int32_t ldb, double beta,
+                                    double *d_C, int32_t ldc, void *stream) {
+    if (M < 0 || N < 0 || K < 0 || !d_C || (K > 0 && (!d_A || !d_B))) return TLR_E_INVAL;
+    if (M == 0 || N == 0) return TLR_OK;
+    if (ldc < M || lda < (trans_a ? K : M) || ldb < (trans_b ? N : K)) return TLR_E_INVAL;
+    hipStream_t s = as_stream(stream);
+    tlr::GemmDesc g{};
+    g.A = d_A;
+    g.B = d_B;
+    g.C = d_C;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.lda = lda > 0 ? lda : 1;
+    g.ldb = ldb > 0 ? ldb : 1;
+    g.ldc = ldc;
+    g.alpha = alpha;
+    g.beta = beta;
+    tlr::GemmDesc *d = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&d), sizeof(g), s) != hipSuccess) return TLR_E_HIP;
+    tlr_status st = TLR_OK;
+    if (hipMemcpyAsync(d, &g, sizeof(g), hipMemcpyHostToDevice, s) != hipSuccess) st = TLR_E_HIP;
+    if (st == TLR_OK) st = tlr::gemm_batched(trans_a != 0, trans_b != 0, d, 1, M, N, s);
+    if (hipStreamSynchronize(s) != hipSuccess) st = TLR_E_HIP;
+    (void)hipFreeAsync(d, s);
+    (void)hipStreamSynchronize(s);
+    return st;
+}
+
+extern "C" tlr_status tlr_diag_svd(int32_t count, int32_t k, const double *d_A, double tol, double *d_S,
+                                   double *d_X, int32_t *d_rank, void *d_scratch, void *stream) {
+    if (count < 0 || k < 1 || k > tlr::kMaxSketch || !d_A || !d_S || !d_X || !d_rank || !d_scratch)
+        return TLR_E_INVAL;
+    if (count == 0) return TLR_OK;
+    hipStream_t s = as_stream(stream);
+    // d_scratch: count * (k*k doubles + 4 int32) + sizeof(DevParams) + descriptors
+    char *w = static_cast<char *>(d_scratch);
+    tlr::DevParams *params = reinterpret_cast<tlr::DevParams *>(w);
+    w += 256;
+    double *R = reinterpret_cast<double *>(w);
+    w += sizeof(double) * (size_t)count * k * k;
+    int32_t *stat = reinterpret_cast<int32_t *>(w);
+    w += tlr::align_up(sizeof(int32_t) * 4 * (size_t)count, 256);
+    tlr::SmallDesc *dd = reinterpret_cast<tlr::SmallDesc *>(w);
+    std::vector<tlr::SmallDesc> h(count);
+    for (int t = 0; t < count; ++t) {
+        tlr::SmallDesc d{};
+        d.A = const_cast<double *>(d_A) + (size_t)t * k * k;
+        d.lda = k;
+        d.R = R + (size_t)t * k * k;
+        d.ldr = k;
+        d.X = d_X + (size_t)t * k * k;
+        d.ldx = k;
+        d.S = d_S + (size_t)t * k;
+        d.rank = stat + 4 * t;
+        d.flag = stat + 4 * t + 2;
+        d.k = k;
+        d.k_full = k;
+        h[t] = d;
+    }
+    if (hipMemsetAsync(params, 0, sizeof(tlr::DevParams), s) != hipSuccess) return TLR_E_HIP;
+    if (hipMemcpyAsync(dd, h.data(), sizeof(tlr::SmallDesc) * count, hipMemcpyHostToDevice, s) != hipSuccess)
+        return TLR_E_HIP;
+    tlr_status st = tlr::jacobi_svd(dd, count, k, tol, 0, k, k, params, s);
+    if (st != TLR_OK) return st;
+    std::vector<int32_t> hs(4 * (size_t)count), hr(count);
+    if (hipMemcpyAsync(hs.data(), stat, sizeof(int32_t) * 4 * count, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return TLR_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return TLR_E_HIP;
+    for (int t = 0; t < count; ++t) hr[t] = hs[4 * t + 1];
+    if (hipMemcpy(d_rank, hr.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice) != hipSuccess) return TLR_E_HIP;
+    return TLR_OK;
+}

@@ -1,0 +1,279 @@
+// Matern tile generation, the sketch test matrix, and the TLR forward solve
+// with the log-determinant / quadratic-form reductions.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace tlr {
+
+bool make_matern_const(double sigma2, double beta, double nu, MaternConst *out) {
+    if (!(sigma2 > 0.0) || !(beta > 0.0) || !(nu > 0.0)) return false;
+    if (!std::isfinite(sigma2) || !std::isfinite(beta) || !std::isfinite(nu)) return false;
+    if (nu > 60.0) return false;
+    MaternConst c{};
+    c.sigma2 = sigma2;
+    c.beta = beta;
+    c.nu = nu;
+    c.kind = (nu == 0.5) ? 1 : (nu == 1.5) ? 2 : (nu == 2.5) ? 3 : 0;
+    const int N = (int)std::floor(nu + 0.5);
+    const double mu = nu - (double)N;
+    c.N = N;
+    c.mu = mu;
+    c.coef = sigma2 / (std::tgamma(nu) * std::pow(2.0, nu - 1.0));
+    const long double gp = std::tgamma(1.0L + (long double)mu);
+    const long double gm = std::tgamma(1.0L - (long double)mu);
+    c.gp = (double)gp;
+    c.gm = (double)gm;
+    c.gam2 = (double)(0.5L * (1.0L / gm + 1.0L / gp));
+    if (std::fabs(mu) < 0.05) {
+        // odd Taylor coefficients of 1/Gamma(1+z) (Abramowitz & Stegun 6.1.34)
+        const double m2 = mu * mu;
+        c.gam1 = -(0.57721566490153286061 +
+                   m2 * (-0.042002635034095235529 +
+                         m2 * (-0.042197734555544336748 +
+                               m2 * (0.0072189432466630995424 +
+                                     m2 * (-0.00021524167411495097282 + m2 * -0.000020134854780788238656)))));
+    } else {
+        c.gam1 = (double)((1.0L / gm - 1.0L / gp) / (2.0L * (long double)mu));
+    }
+    c.fact = (mu == 0.0) ? 1.0 : (double)((long double)mu * 3.14159265358979323846264338327950288L /
+                                          std::sin((long double)mu * 3.14159265358979323846264338327950288L));
+    *out = c;
+    return true;
+}
+
+namespace {
+
+// One work-group per (tile, group of 8 columns): threads run down the rows,
+// so the stores of a column are contiguous.
+__global__ __launch_bounds__(256) void k_gen_tiles(const GenDesc *__restrict__ descs, int nb, int64_t n,
+                                                   const double *__restrict__ x, const double *__restrict__ y,
+                                                   MaternConst c) {
+    const GenDesc d = descs[blockIdx.y];
+    const int q0 = blockIdx.x * 8;
+    for (int q = q0; q < q0 + 8 && q < nb; ++q) {
+        const int64_t gj = d.col0 + q;
+        const bool jin = gj < n;
+        const double xj = jin ? x[gj] : 0.0, yj = jin ? y[gj] : 0.0;
+        double *col = d.dst + (int64_t)q * d.ld;
+        for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+            const int64_t gi = d.row0 + r;
+            double v;
+            if (gi >= n || !jin) {
+                v = (gi == gj) ? 1.0 : 0.0;  // identity padding of the ragged last tile
+            } else if (gi == gj) {
+                v = c.sigma2;
+            } else {
+                const double dx = x[gi] - xj, dy = y[gi] - yj;
+                v = matern_cov(sqrt(dx * dx + dy * dy), c);
+            }
+            col[r] = v;
+        }
+    }
+}
+
+// Counter-based standard normals: SplitMix64 pairs -> Box-Muller.
+__device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_gaussian(double *out, int64_t count, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t a = mix64(seed + (2 * (uint64_t)i + 1) * 0x9E3779B97F4A7C15ull);
+    const uint64_t b = mix64(seed + (2 * (uint64_t)i + 2) * 0x9E3779B97F4A7C15ull);
+    const double u1 = ((double)(a >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);
+    out[i] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+__global__ void k_split_locs(const double *__restrict__ locs, int64_t n, int64_t npad, double *__restrict__ x,
+                             double *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    x[i] = (i < n) ? locs[2 * i] : 0.0;
+    y[i] = (i < n) ? locs[2 * i + 1] : 0.0;
+}
+
+__global__ void k_pad_copy(const double *__restrict__ z, int64_t n, int64_t npad, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < npad) out[i] = (i < n) ? z[i] : 0.0;
+}
+
+// y <- L^-1 y for one dense lower-triangular nb x nb tile (one work-group).
+__global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L, int nb,
+                                                   double *__restrict__ yv, const DevParams *params) {
+    __shared__ double xb[64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (params->status != 0) return;
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+        const int bs = (nb - b0 < 64) ? nb - b0 : 64;
+        if (wave == 0) {
+            double v = (lane < bs) ? yv[b0 + lane] : 0.0;
+            for (int r = 0; r < bs; ++r) {
+                double xr = 0.0;
+                if (lane == r) xr = v / L[(b0 + r) + (int64_t)(b0 + r) * nb];
+                xr = __shfl(xr, r, 64);
+                if (lane == r) v = xr;
+                if (lane > r && lane < bs) v -= L[(b0 + lane) + (int64_t)(b0 + r) * nb] * xr;
+            }
+            if (lane < bs) {
+                xb[lane] = v;
+                yv[b0 + lane] = v;
+            }
+        }
+        __syncthreads();
+        for (int row = b0 + bs + tid; row < nb; row += blockDim.x) {
+            double acc = 0.0;
+            for (int c = 0; c < bs; ++c) acc += L[row + (int64_t)(b0 + c) * nb] * xb[c];
+            yv[row] -= acc;
+        }
+        __syncthreads();
+    }
+}
+
+struct GemvDesc {
+    const double *U;
+    const double *V;
+    const double *yj;
+    double *yi;
+    const int32_t *r_dev;
+};
+
+// y_i <- y_i - U (V^T y_j) for a batch of low-rank tiles (one work-group each).
+__global__ __launch_bounds__(256) void k_lr_gemv(const GemvDesc *__restrict__ descs, int nb,
+                                                 const DevParams *params) {
+    __shared__ double t[512];
+    const GemvDesc d = descs[blockIdx.x];
+    const int r = *d.r_dev;
+    if (r <= 0 || params->status != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int c = wave; c < r; c += 4) {
+        const double *v = d.V + (int64_t)c * nb;
+        double acc = 0.0;
+        for (int q = lane; q < nb; q += 64) acc += v[q] * d.yj[q];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) t[c] = acc;
+    }
+    __syncthreads();
+    for (int row = tid; row < nb; row += blockDim.x) {
+        double acc = 0.0;
+        for (int c = 0; c < r; ++c) acc += d.U[row + (int64_t)c * nb] * t[c];
+        d.yi[row] -= acc;
+    }
+}
+
+// out = {logdet, quad, loglik}; fixed-order reduction (bitwise reproducible).
+__global__ __launch_bounds__(1024) void k_logdet_quad(const double *__restrict__ diag, int nb, int nt, int64_t n,
+                                                      const double *__restrict__ yv, const DevParams *params,
+                                                      double *__restrict__ out) {
+    __shared__ double s_ld[1024], s_q[1024];
+    const int tid = threadIdx.x;
+    double ld = 0.0, q = 0.0;
+    for (int64_t i = tid; i < n; i += 1024) {
+        const int64_t k = i / nb, r = i % nb;
+        ld += log(diag[k * (int64_t)nb * nb + r + r * (int64_t)nb]);
+        q += yv[i] * yv[i];
+    }
+    s_ld[tid] = ld;
+    s_q[tid] = q;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (tid < s) {
+            s_ld[tid] += s_ld[tid + s];
+            s_q[tid] += s_q[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double logdet = 2.0 * s_ld[0];
+        const double quad = s_q[0];
+        out[0] = logdet;
+        out[1] = quad;
+        const double ll = -0.5 * (double)n * 1.8378770664093454836 - 0.5 * logdet - 0.5 * quad;
+        out[2] = (params->status != 0 || !isfinite(ll)) ? -INFINITY : ll;
+    }
+    (void)nt;
+}
+
+}  // namespace
+
+tlr_status gen_tiles_launch(const GenDesc *d_descs, int count, int nb, int64_t n, const double *x,
+                            const double *y, const MaternConst &c, hipStream_t s) {
+    if (count <= 0) return TLR_OK;
+    hipLaunchKernelGGL(k_gen_tiles, dim3((unsigned)cdiv(nb, 8), count), dim3(256), 0, s, d_descs, nb, n, x, y, c);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status gaussian_fill(double *out, int64_t count, uint64_t seed, hipStream_t s) {
+    if (count <= 0) return TLR_OK;
+    hipLaunchKernelGGL(k_gaussian, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, s, out, count, seed);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status split_locs(const double *locs, int64_t n, int64_t npad, double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_split_locs, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, locs, n, npad, x, y);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status pad_copy(const double *z, int64_t n, int64_t npad, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pad_copy, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, z, n, npad, out);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status trsv_tile(const double *L, int nb, double *yv, const DevParams *params, hipStream_t s) {
+    hipLaunchKernelGGL(k_trsv_tile, dim3(1), dim3(256), 0, s, L, nb, yv, params);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status lr_gemv(const void *d_descs, int count, int nb, const DevParams *params, hipStream_t s) {
+    if (count <= 0) return TLR_OK;
+    hipLaunchKernelGGL(k_lr_gemv, dim3(count), dim3(256), 0, s, static_cast<const GemvDesc *>(d_descs), nb,
+                       params);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+size_t gemv_desc_bytes() { return sizeof(GemvDesc); }
+
+void make_gemv_desc(void *dst, const double *U, const double *V, const double *yj, double *yi,
+                    const int32_t *r_dev) {
+    GemvDesc g{U, V, yj, yi, r_dev};
+    *static_cast<GemvDesc *>(dst) = g;
+}
+
+tlr_status logdet_quad(const double *diag, int nb, int nt, int64_t n, const double *yv, const DevParams *params,
+                       double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_logdet_quad, dim3(1), dim3(1024), 0, s, diag, nb, nt, n, yv, params, out);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+namespace {
+__global__ void k_copy_panel(const double *__restrict__ src, int64_t lds_, double *__restrict__ dst,
+                             int64_t ldd, int rows, const int32_t *cols_dev) {
+    const int cols = *cols_dev;
+    const int c = blockIdx.y;
+    if (c >= cols) return;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x)
+        dst[r + c * ldd] = src[r + c * lds_];
+}
+}  // namespace
+
+tlr_status copy_panel(const double *src, int64_t lds_, double *dst, int64_t ldd, int rows, const int32_t *cols_dev,
+                      int max_cols, hipStream_t s) {
+    if (max_cols <= 0) return TLR_OK;
+    hipLaunchKernelGGL(k_copy_panel, dim3((unsigned)cdiv(rows, 256), max_cols), dim3(256), 0, s, src, lds_, dst,
+                       ldd, rows, cols_dev);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+}  // namespace tlr

@@ -1,0 +1,112 @@
+// Host-side launchers of the library's device kernels.
+#pragma once
+
+#include "common.h"
+#include "matern.h"
+
+namespace tlr {
+
+// One product C = alpha * op(A) * op(B) + beta * C of a batched launch.
+// Matrices are column-major.  op(A) is M x K, op(B) is K x N.  When an
+// override pointer is set, the device value replaces the field (sizes that
+// are only known on the device, e.g. a rank computed by an earlier kernel).
+struct GemmDesc {
+    const double *A;
+    const double *B;
+    double *C;
+    const int32_t *M_dev;
+    const int32_t *N_dev;
+    const int32_t *K_dev;
+    int32_t M, N, K;
+    int32_t lda, ldb, ldc;
+    double alpha, beta;
+};
+
+// trans_a / trans_b: op(X) = X^T.  max_m, max_n bound every product's M, N
+// (they size the grid; products smaller than the bound exit early).
+tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int count, int max_m,
+                        int max_n, hipStream_t s);
+
+// Small dense problems, one work-group each.
+struct SmallDesc {
+    double *A;        // k x k input (lda)
+    double *R;        // k x k output (ldr)
+    double *X;        // k x k output: left singular vectors (ldx)
+    double *S;        // k output: singular values
+    double *Y;        // m x k panel (ldy) for the row solves
+    int32_t *rank;    // out: rank at tol (Jacobi)
+    int32_t *flag;    // out: 1 if the sketch was too narrow (Jacobi)
+    const int32_t *k_dev;  // optional device k
+    int32_t k, lda, ldr, ldx, m, ldy;
+    int32_t k_full;        // sketch width at which the sample is exact
+    int32_t tile_i, tile_j;
+};
+
+// R = upper Cholesky factor of A (+ shift I).  mode 1: shift = 11 (m k +
+// k(k+1)) u trace(A); mode 2: no shift, pivots below 1e-12 max diag(A) deflate
+// their column; mode 0: plain.  A is read-only.
+tlr_status chol_small(const SmallDesc *d_descs, int count, int max_k, int mode, DevParams *params,
+                      hipStream_t s);
+// Y <- Y R^-1 (R upper triangular k x k), in place, row by row.
+tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, hipStream_t s);
+// Largest sketch width any kernel accepts.
+constexpr int kMaxSketch = 512;
+
+// One-sided Jacobi SVD of A (k x k): S descending, X = left singular vectors,
+// R = k x k scratch (used when k is too large for LDS),
+// rank = #{S > tol}; flag = 1 when fewer than `min_tail` values are <= tol
+// and k < k_full (the sample was too narrow to resolve the threshold).
+tlr_status jacobi_svd(const SmallDesc *d_descs, int count, int max_k, double tol, int min_tail,
+                      int k_full, int rank_cap, DevParams *params, hipStream_t s);
+
+// Dense diagonal-tile kernels (nb x nb, column-major, ld = nb).
+// Blocked Cholesky (block 64): the trailing updates use ceil(nb/64) GEMM
+// descriptors built by potrf_tile_descs and staged on the device by the caller.
+void potrf_tile_descs(double *A, int nb, GemmDesc *h);
+tlr_status potrf_tile(double *A, int nb, int tile, DevParams *params, const GemmDesc *d_desc, hipStream_t s);
+
+struct CopyDesc {
+    const double *src;
+    double *dst;
+    int64_t words;
+};
+tlr_status copy_batched(const CopyDesc *d_descs, int count, int64_t max_words, hipStream_t s);
+// B_t <- L^-1 B_t for `count` right-hand-side panels (nb x cols_t, ld nb),
+// L lower (nb x nb).  descs: A = L (shared), Y = B_t, k = cols_t.
+// d_gemm / h_gemm: room for count * ceil(nb/64) descriptors.
+tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, const SmallDesc *h_descs,
+                           int count, int max_cols, GemmDesc *d_gemm, GemmDesc *h_gemm, hipStream_t s);
+
+// Matern tile generation.
+struct GenDesc {
+    double *dst;        // nb x nb, column-major, ld
+    int32_t row0, col0; // global start indices
+    int32_t ld;
+    int32_t diag;       // 1 for a diagonal tile
+};
+tlr_status gen_tiles_launch(const GenDesc *d_descs, int count, int nb, int64_t n, const double *x,
+                            const double *y, const MaternConst &c, hipStream_t s);
+
+// Misc.
+tlr_status gaussian_fill(double *out, int64_t count, uint64_t seed, hipStream_t s);
+tlr_status split_locs(const double *locs, int64_t n, int64_t npad, double *x, double *y, hipStream_t s);
+tlr_status pad_copy(const double *z, int64_t n, int64_t npad, double *out, hipStream_t s);
+tlr_status trsv_tile(const double *L, int nb, double *yv, const DevParams *params, hipStream_t s);
+size_t gemv_desc_bytes();
+void make_gemv_desc(void *dst, const double *U, const double *V, const double *yj, double *yi,
+                    const int32_t *r_dev);
+tlr_status lr_gemv(const void *d_descs, int count, int nb, const DevParams *params, hipStream_t s);
+tlr_status logdet_quad(const double *diag, int nb, int nt, int64_t n, const double *yv, const DevParams *params,
+                       double *out, hipStream_t s);
+// dst[:, c] = src[:, c] for c < *cols_dev (rows x cols panels).
+tlr_status copy_panel(const double *src, int64_t lds, double *dst, int64_t ldd, int rows, const int32_t *cols_dev,
+                      int max_cols, hipStream_t s);
+
+// Orderings.
+size_t reorder_ws_bytes(int64_t n, tlr_ordering kind);
+tlr_status reorder(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed, uint32_t flags,
+                   int32_t *d_perm, void *d_ws, size_t ws_bytes, hipStream_t s);
+tlr_status apply_perm(const int32_t *d_perm, int64_t n, const double *d_locs, const double *d_z,
+                      double *d_locs_out, double *d_z_out, int dequant, hipStream_t s);
+
+}  // namespace tlr

@@ -1,0 +1,822 @@
+// Plan, workspace layout and the host-side drivers of the TLR likelihood:
+// covariance generation, per-tile randomised compression, the left-looking
+// TLR Cholesky factorisation and the forward solve.
+//
+// Workspace (caller-owned device memory, offsets fixed by the plan):
+//   params    DevParams + Matern constants + hint marker
+//   x, y      ordered coordinates, structure-of-arrays, padded to nt*nb
+//   diag      nt dense nb x nb diagonal tiles (column-major)
+//   rsig, rL  nt x nt int32 rank tables: compressed Sigma, current factor
+//   tstat     per off-diagonal tile: {rank used, numerical rank, retry flag, -}
+//   slots     per off-diagonal tile (i > j, index i(i-1)/2 + j): U then V,
+//             each nb x maxrank column-major
+//   yvec      padded solve vector
+//   omega     nb x kmax standard-normal test matrix of the range finder
+//   desc      kernel descriptor staging area
+//   arena     per-wave scratch (dense tiles, sketches, small matrices)
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "kernels.h"
+
+struct tlr_plan_s {
+    int64_t n, npad, ntiles;
+    int nb, nt, rcap, kmax, pover, min_tail, k0;
+    tlr_precision prec;
+    uint32_t flags;
+    size_t off_params, off_x, off_y, off_diag, off_rsig, off_rL, off_tstat, off_slots, off_yvec, off_omega,
+        off_desc, off_arena;
+    size_t desc_bytes, arena_bytes, ws_bytes;
+};
+
+namespace tlr {
+namespace {
+
+constexpr uint64_t kHintMagic = 0x544c524d4c453031ull;  // ranks in rsig are valid hints
+constexpr uint64_t kSketchSeed = 0x5eed5ca1ab1e2024ull;
+
+struct ParamsBlock {
+    DevParams dp;
+    MaternConst mc;
+    uint64_t hint_magic;
+    double tol;
+};
+
+inline int64_t tile_index(int i, int j) { return (int64_t)i * (i - 1) / 2 + j; }
+
+bool debug_enabled() {
+    static const bool on = [] {
+        const char *e = std::getenv("TLR_DEBUG");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
+struct Ctx {
+    const tlr_plan_s *p;
+    char *ws;
+    hipStream_t s;
+    std::vector<char> hdesc;
+    size_t desc_used = 0;
+    size_t arena_used = 0;
+
+    Ctx(const tlr_plan_s *plan, void *w, hipStream_t st) : p(plan), ws(static_cast<char *>(w)), s(st) {
+        hdesc.resize(plan->desc_bytes);
+    }
+    DevParams *params() const { return reinterpret_cast<DevParams *>(ws + p->off_params); }
+    ParamsBlock *pblock() const { return reinterpret_cast<ParamsBlock *>(ws + p->off_params); }
+    double *x() const { return reinterpret_cast<double *>(ws + p->off_x); }
+    double *y() const { return reinterpret_cast<double *>(ws + p->off_y); }
+    double *diag(int k) const {
+        return reinterpret_cast<double *>(ws + p->off_diag) + (int64_t)k * p->nb * p->nb;
+    }
+    int32_t *rsig() const { return reinterpret_cast<int32_t *>(ws + p->off_rsig); }
+    int32_t *rL() const { return reinterpret_cast<int32_t *>(ws + p->off_rL); }
+    int32_t *tstat(int64_t t) const { return reinterpret_cast<int32_t *>(ws + p->off_tstat) + 4 * t; }
+    double *U(int i, int j) const {
+        return reinterpret_cast<double *>(ws + p->off_slots) + tile_index(i, j) * 2 * (int64_t)p->nb * p->rcap;
+    }
+    double *V(int i, int j) const { return U(i, j) + (int64_t)p->nb * p->rcap; }
+    double *yvec() const { return reinterpret_cast<double *>(ws + p->off_yvec); }
+    double *omega() const { return reinterpret_cast<double *>(ws + p->off_omega); }
+
+    // Stage a descriptor array and copy it to the device; nullptr when full.
+    template <class T>
+    T *push(const T *data, size_t count) {
+        const size_t bytes = align_up(sizeof(T) * std::max<size_t>(count, 1), 256);
+        if (desc_used + bytes > p->desc_bytes) return nullptr;
+        char *h = hdesc.data() + desc_used;
+        std::memcpy(h, data, sizeof(T) * count);
+        T *d = reinterpret_cast<T *>(ws + p->off_desc + desc_used);
+        if (hipMemcpyAsync(d, h, sizeof(T) * count, hipMemcpyHostToDevice, s) != hipSuccess) return nullptr;
+        desc_used += bytes;
+        return d;
+    }
+    template <class T>
+    T *push(const std::vector<T> &v) {
+        return push(v.data(), v.size());
+    }
+    double *alloc(size_t words) {
+        const size_t bytes = align_up(std::max<size_t>(words, 1) * sizeof(double), 256);
+        if (arena_used + bytes > p->arena_bytes) return nullptr;
+        double *d = reinterpret_cast<double *>(ws + p->off_arena + arena_used);
+        arena_used += bytes;
+        return d;
+    }
+    tlr_status sync_reset() {
+        TLR_HIP(hipStreamSynchronize(s));
+        desc_used = 0;
+        return TLR_OK;
+    }
+    tlr_status read_status(int *code) {
+        int32_t st = 0;
+        TLR_HIP(hipMemcpyAsync(&st, &params()->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        TLR_HIP(hipStreamSynchronize(s));
+        *code = st;
+        return TLR_OK;
+    }
+};
+
+#define TLR_PUSH(ptr, ctx, vec)                          \
+    auto ptr = (ctx).push(vec);                          \
+    do {                                                 \
+        if (!(ptr)) return TLR_E_NOMEM;                  \
+    } while (0)
+
+GemmDesc gd(const double *A, int lda, const double *B, int ldb, double *C, int ldc, int M, int N, int K,
+            double alpha, double beta) {
+    GemmDesc g{};
+    g.A = A;
+    g.B = B;
+    g.C = C;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.lda = std::max(lda, 1);
+    g.ldb = std::max(ldb, 1);
+    g.ldc = std::max(ldc, 1);
+    g.alpha = alpha;
+    g.beta = beta;
+    return g;
+}
+
+tlr_status launch_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v) {
+    if (v.empty()) return TLR_OK;
+    int mm = 0, mn = 0;
+    for (const auto &g : v) {
+        mm = std::max(mm, g.M_dev ? c.p->kmax : g.M);
+        mn = std::max(mn, g.N_dev ? c.p->rcap : g.N);
+    }
+    if (mm <= 0 || mn <= 0) return TLR_OK;
+    for (size_t off = 0; off < v.size(); off += 65535) {
+        const size_t cnt = std::min<size_t>(65535, v.size() - off);
+        auto *d = c.push(v.data() + off, cnt);
+        if (!d) return TLR_E_NOMEM;
+        TLR_TRY(gemm_batched(ta, tb, d, (int)cnt, mm, mn, c.s));
+    }
+    return TLR_OK;
+}
+
+// One tile compression problem for the randomised range finder.
+struct Job {
+    int i, j, k, kfull;
+    // operator: dense tile A, or the Schur form U V^T - Xi Yj^T
+    const double *A = nullptr;
+    const double *Uop = nullptr, *Vop = nullptr;
+    int r = 0;
+    const double *Xi = nullptr;
+    // outputs
+    double *Uout = nullptr, *Vout = nullptr;
+    int32_t *stat = nullptr;
+    // buffers
+    double *Yb = nullptr, *Zb = nullptr, *G = nullptr, *T = nullptr, *Rt = nullptr, *Xs = nullptr, *S = nullptr,
+           *P = nullptr, *H = nullptr, *F = nullptr;
+    double *Rp[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+size_t job_words(int nb, int k, int r, int R, bool dense) {
+    size_t w = 0;
+    if (dense) w += (size_t)nb * nb;
+    w += 2 * (size_t)nb * k;          // Yb, Zb
+    w += 9 * (size_t)k * k;           // G R1..R4 T Rt Xs P
+    w += (size_t)k;                   // S
+    w += (size_t)std::max(r, 1) * k;  // H
+    w += (size_t)std::max(R, 1) * k;  // F
+    return w + 16 * 64;               // alignment slack
+}
+
+bool alloc_job(Ctx &c, Job &jb, int R) {
+    const int nb = c.p->nb, k = jb.k;
+    jb.Yb = c.alloc((size_t)nb * k);
+    jb.Zb = c.alloc((size_t)nb * k);
+    jb.G = c.alloc((size_t)k * k);
+    for (int q = 0; q < 4; ++q) jb.Rp[q] = c.alloc((size_t)k * k);
+    jb.T = c.alloc((size_t)k * k);
+    jb.Rt = c.alloc((size_t)k * k);
+    jb.Xs = c.alloc((size_t)k * k);
+    jb.P = c.alloc((size_t)k * k);
+    jb.S = c.alloc((size_t)k);
+    jb.H = c.alloc((size_t)std::max(jb.r, 1) * k);
+    jb.F = c.alloc((size_t)std::max(R, 1) * k);
+    return jb.Yb && jb.Zb && jb.G && jb.Rp[0] && jb.Rp[1] && jb.Rp[2] && jb.Rp[3] && jb.T && jb.Rt && jb.Xs &&
+           jb.P && jb.S && jb.H && jb.F;
+}
+
+// out_t = op_t(in_t) (trans: op^T).  in_t == nullptr means the test matrix.
+tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega, bool into_z,
+                    const double *Yj, int Rj) {
+    const int nb = c.p->nb;
+    std::vector<GemmDesc> g1, g2, g3;
+    const bool dense = jobs.front().A != nullptr;
+    for (auto &jb : jobs) {
+        const double *in = from_omega ? c.omega() : (into_z ? jb.Yb : jb.Zb);
+        double *out = into_z ? jb.Zb : jb.Yb;
+        if (dense) {
+            g1.push_back(gd(jb.A, nb, in, nb, out, nb, nb, jb.k, nb, 1.0, 0.0));
+        } else {
+            // H = (trans ? U : V)^T in ; F = (trans ? Xi : Yj)^T in
+            const double *left = trans ? jb.Uop : jb.Vop;
+            const double *big = trans ? jb.Xi : Yj;
+            g1.push_back(gd(left, nb, in, nb, jb.H, std::max(jb.r, 1), jb.r, jb.k, nb, 1.0, 0.0));
+            g1.push_back(gd(big, nb, in, nb, jb.F, std::max(Rj, 1), Rj, jb.k, nb, 1.0, 0.0));
+            // out = (trans ? V : U) H ; out -= (trans ? Yj : Xi) F
+            const double *right = trans ? jb.Vop : jb.Uop;
+            const double *big2 = trans ? Yj : jb.Xi;
+            g2.push_back(gd(right, nb, jb.H, std::max(jb.r, 1), out, nb, nb, jb.k, jb.r, 1.0, 0.0));
+            g3.push_back(gd(big2, nb, jb.F, std::max(Rj, 1), out, nb, nb, jb.k, Rj, -1.0, 1.0));
+        }
+    }
+    if (dense) return launch_gemms(c, trans, false, g1);
+    TLR_TRY(launch_gemms(c, true, false, g1));
+    TLR_TRY(launch_gemms(c, false, false, g2));
+    return launch_gemms(c, false, false, g3);
+}
+
+// CholeskyQR of each job's panel (nb x k) in place, four passes: two with
+// the stabilising shift of shifted CholeskyQR (Fukaya et al. 2020) -- the
+// panels are rank-deficient by construction (sketch width above the rank)
+// and each shifted pass lifts the directions it cannot resolve yet -- then two
+// plain passes with deflation of null directions, which restore
+// orthonormality to rounding level.  Optionally R = R4 R3 R2 R1 (panel = Q R).
+tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r) {
+    const int nb = c.p->nb;
+    int kmx = 0;
+    for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
+    for (int it = 0; it < 4; ++it) {
+        std::vector<GemmDesc> gram;
+        std::vector<SmallDesc> sd;
+        for (auto &jb : jobs) {
+            double *Yp = on_z ? jb.Zb : jb.Yb;
+            gram.push_back(gd(Yp, nb, Yp, nb, jb.G, jb.k, jb.k, jb.k, nb, 1.0, 0.0));
+            SmallDesc d{};
+            d.A = jb.G;
+            d.lda = jb.k;
+            d.R = jb.Rp[it];
+            d.ldr = jb.k;
+            d.Y = Yp;
+            d.ldy = nb;
+            d.m = nb;
+            d.k = jb.k;
+            d.tile_i = jb.i;
+            d.tile_j = jb.j;
+            sd.push_back(d);
+        }
+        TLR_TRY(launch_gemms(c, true, false, gram));
+        TLR_PUSH(dsd, c, sd);
+        TLR_TRY(chol_small(dsd, (int)sd.size(), kmx, it < 2 ? 1 : 2, c.params(), c.s));
+        TLR_TRY(trsm_rows(dsd, (int)sd.size(), nb, kmx, c.s));
+    }
+    if (want_r) {
+        // Rt = R4 R3 R2 R1, accumulated through T
+        std::vector<GemmDesc> a, b, d2;
+        for (auto &jb : jobs) {
+            a.push_back(gd(jb.Rp[3], jb.k, jb.Rp[2], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+            b.push_back(gd(jb.T, jb.k, jb.Rp[1], jb.k, jb.Rt, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+            d2.push_back(gd(jb.Rt, jb.k, jb.Rp[0], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+        }
+        TLR_TRY(launch_gemms(c, false, false, a));
+        TLR_TRY(launch_gemms(c, false, false, b));
+        TLR_TRY(launch_gemms(c, false, false, d2));
+        for (auto &jb : jobs) std::swap(jb.Rt, jb.T);
+    }
+    return TLR_OK;
+}
+
+// Range finder with one power step:  Y = T W  (W = Gaussian), Q1 = orth(Y);
+// Z = T^T Q1, Q2 = orth(Z);  W = T Q2 = Qw Rt;  Rt = X S Yr^T (Jacobi);
+// T ~ Qw X_r S_r Yr_r^T Q2^T  =>  U = Qw X_r,  V = Q2 (Rt^T X_r).
+tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, int Rj) {
+    if (jobs.empty()) return TLR_OK;
+    const int nb = c.p->nb;
+    int kmx = 0;
+    for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
+    TLR_TRY(apply_op(c, jobs, false, true, false, Yj, Rj));   // Yb = T W
+    TLR_TRY(cholqr(c, jobs, false, false));                  // Yb = Q1
+    TLR_TRY(apply_op(c, jobs, true, false, true, Yj, Rj));    // Zb = T^T Q1
+    TLR_TRY(cholqr(c, jobs, true, false));                   // Zb = Q2
+    TLR_TRY(apply_op(c, jobs, false, false, false, Yj, Rj));  // Yb = T Q2
+    TLR_TRY(cholqr(c, jobs, false, true));                   // Yb = Qw, Rt
+    std::vector<SmallDesc> sd;
+    for (auto &jb : jobs) {
+        SmallDesc d{};
+        d.A = jb.Rt;
+        d.lda = jb.k;
+        d.R = jb.G;  // scratch
+        d.ldr = jb.k;
+        d.X = jb.Xs;
+        d.ldx = jb.k;
+        d.S = jb.S;
+        d.rank = jb.stat;
+        d.flag = jb.stat + 2;
+        d.k = jb.k;
+        d.k_full = jb.kfull;
+        d.tile_i = jb.i;
+        d.tile_j = jb.j;
+        sd.push_back(d);
+    }
+    TLR_PUSH(dsd, c, sd);
+    TLR_TRY(jacobi_svd(dsd, (int)sd.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s));
+    std::vector<GemmDesc> gu, gp, gv;
+    for (auto &jb : jobs) {
+        GemmDesc a = gd(jb.Yb, nb, jb.Xs, jb.k, jb.Uout, nb, nb, 0, jb.k, 1.0, 0.0);
+        a.N_dev = jb.stat;
+        gu.push_back(a);
+        GemmDesc b = gd(jb.Rt, jb.k, jb.Xs, jb.k, jb.P, jb.k, jb.k, 0, jb.k, 1.0, 0.0);
+        b.N_dev = jb.stat;
+        gp.push_back(b);
+        GemmDesc v = gd(jb.Zb, nb, jb.P, jb.k, jb.Vout, nb, nb, 0, jb.k, 1.0, 0.0);
+        v.N_dev = jb.stat;
+        gv.push_back(v);
+    }
+    TLR_TRY(launch_gemms(c, false, false, gu));
+    TLR_TRY(launch_gemms(c, true, false, gp));
+    TLR_TRY(launch_gemms(c, false, false, gv));
+    return TLR_OK;
+}
+
+int tile_rows(const tlr_plan_s *p, int i) {
+    const int64_t r = p->n - (int64_t)i * p->nb;
+    return (int)std::min<int64_t>(r, p->nb);
+}
+
+int clamp_k(const tlr_plan_s *p, int want, int kfull) {
+    int cap = std::min(p->kmax, kfull);
+    int k = std::max(want, std::min(p->k0, cap));
+    k = (k + 7) / 8 * 8;
+    return std::max(1, std::min(k, cap));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan --
+
+tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precision prec, uint32_t flags) {
+    if (!out) return TLR_E_INVAL;
+    *out = nullptr;
+    if (n < 1 || nb < 16 || nb > 4096) return TLR_E_INVAL;
+    if (prec != TLR_FP64 && prec != TLR_MIXED_FP32) return TLR_E_INVAL;
+    if (prec != TLR_FP64) return TLR_E_UNSUPPORTED;
+    auto *p = new tlr_plan_s{};
+    p->n = n;
+    p->nb = nb;
+    p->nt = (int)cdiv(n, nb);
+    p->npad = (int64_t)p->nt * nb;
+    p->ntiles = (int64_t)p->nt * (p->nt - 1) / 2;
+    p->pover = 16;
+    p->min_tail = 8;
+    p->k0 = 32;
+    int rcap = (maxrank <= 0) ? nb / 2 : std::min(maxrank, nb);
+    rcap = std::max(1, std::min(rcap, kMaxSketch - p->pover));
+    p->rcap = rcap;
+    p->kmax = std::min({nb, rcap + p->pover, kMaxSketch});
+    p->prec = prec;
+    p->flags = flags;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    p->off_params = take(sizeof(ParamsBlock));
+    p->off_x = take(sizeof(double) * p->npad);
+    p->off_y = take(sizeof(double) * p->npad);
+    p->off_diag = take(sizeof(double) * (size_t)p->nt * nb * nb);
+    p->off_rsig = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
+    p->off_rL = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
+    p->off_tstat = take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(p->ntiles, 1));
+    p->off_slots = take(sizeof(double) * 2 * (size_t)nb * rcap * (size_t)p->ntiles);
+    p->off_yvec = take(sizeof(double) * p->npad);
+    p->off_omega = take(sizeof(double) * (size_t)nb * p->kmax);
+    p->desc_bytes = 8u << 20;
+    p->off_desc = take(p->desc_bytes);
+    // arena: one full wave of dense-tile jobs, plus the factorisation's
+    // per-column panels, bounded to keep small problems small
+    const size_t per_job = job_words(nb, p->kmax, rcap, 0, true) * sizeof(double);
+    const size_t col_panels = sizeof(double) * (size_t)nb * (size_t)std::max(1, p->nt - 1) * rcap * 3;
+    size_t arena = std::max<size_t>(per_job * (size_t)std::min<int64_t>(std::max<int64_t>(p->ntiles, 1), 64), col_panels + per_job * 4);
+    arena = std::max<size_t>(arena, 64u << 20);
+    arena = std::min<size_t>(arena, (size_t)16 << 30);
+    p->arena_bytes = arena;
+    p->off_arena = take(arena);
+    p->ws_bytes = off;
+    *out = p;
+    return TLR_OK;
+}
+
+void plan_destroy(tlr_plan p) { delete p; }
+
+size_t plan_ws_bytes(tlr_plan p) { return p ? p->ws_bytes : 0; }
+
+// ------------------------------------------------------------ generation --
+
+tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    if (!p || !d_locs || !d_ws) return TLR_E_INVAL;
+    if (ws_bytes < p->ws_bytes) return TLR_E_NOMEM;
+    MaternConst mc{};
+    if (!make_matern_const(th.sigma2, th.beta, th.nu, &mc)) return TLR_E_INVAL;
+    Ctx c(p, d_ws, s);
+    ParamsBlock hb{};
+    TLR_HIP(hipMemcpyAsync(&hb, c.pblock(), sizeof(ParamsBlock), hipMemcpyDeviceToHost, s));
+    TLR_HIP(hipStreamSynchronize(s));
+    const uint64_t keep_magic = hb.hint_magic;
+    hb = ParamsBlock{};
+    hb.dp.sigma2 = th.sigma2;
+    hb.dp.beta = th.beta;
+    hb.dp.nu = th.nu;
+    hb.dp.status = 0;
+    hb.dp.fail_i = hb.dp.fail_j = -1;
+    hb.mc = mc;
+    hb.hint_magic = keep_magic;
+    TLR_HIP(hipMemcpyAsync(c.pblock(), &hb, sizeof(ParamsBlock), hipMemcpyHostToDevice, s));
+    TLR_TRY(split_locs(d_locs, p->n, p->npad, c.x(), c.y(), s));
+    std::vector<GenDesc> g;
+    for (int k = 0; k < p->nt; ++k) g.push_back(GenDesc{c.diag(k), k * p->nb, k * p->nb, p->nb, 1});
+    TLR_PUSH(dg, c, g);
+    TLR_TRY(gen_tiles_launch(dg, (int)g.size(), p->nb, p->n, c.x(), c.y(), mc, s));
+    TLR_TRY(gaussian_fill(c.omega(), (int64_t)p->nb * p->kmax, kSketchSeed, s));
+    TLR_HIP(hipStreamSynchronize(s));  // host descriptors above go out of scope
+    return TLR_OK;
+}
+
+// ------------------------------------------------------------ compression --
+
+tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks, hipStream_t s) {
+    if (!p || !d_ws) return TLR_E_INVAL;
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return TLR_E_INVAL;
+    if (ws_bytes < p->ws_bytes) return TLR_E_NOMEM;
+    Ctx c(p, d_ws, s);
+    const int nt = p->nt, nb = p->nb;
+    ParamsBlock hb{};
+    TLR_HIP(hipMemcpyAsync(&hb, c.pblock(), sizeof(ParamsBlock), hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> hint((size_t)nt * nt, -1), ranks((size_t)nt * nt, 0);
+    TLR_HIP(hipMemcpyAsync(hint.data(), c.rsig(), sizeof(int32_t) * hint.size(), hipMemcpyDeviceToHost, s));
+    TLR_HIP(hipStreamSynchronize(s));
+    // Every tile starts from the same sketch width (no state carried between
+    // evaluations), so the result depends on the inputs only.
+    const bool hints_ok = false;
+    const MaternConst mc = hb.mc;
+    {
+        double t = tol;
+        TLR_HIP(hipMemcpyAsync(&c.pblock()->tol, &t, sizeof(double), hipMemcpyHostToDevice, s));
+        TLR_HIP(hipStreamSynchronize(s));
+    }
+    struct Pending {
+        int i, j, k;
+    };
+    std::vector<Pending> pending;
+    for (int i = 1; i < nt; ++i)
+        for (int j = 0; j < i; ++j) {
+            const int kfull = std::min(tile_rows(p, i), tile_rows(p, j));
+            const int h = hints_ok ? hint[(size_t)i * nt + j] : -1;
+            const int want = (h >= 0) ? h + p->pover : p->k0;
+            pending.push_back({i, j, clamp_k(p, want, kfull)});
+        }
+    while (!pending.empty()) {
+        std::vector<Pending> retry;
+        size_t pos = 0;
+        while (pos < pending.size()) {
+            c.arena_used = 0;
+            std::vector<Job> jobs;
+            std::vector<GenDesc> gens;
+            while (pos < pending.size()) {
+                const Pending &pt = pending[pos];
+                const size_t need = job_words(nb, pt.k, 0, 0, true) * sizeof(double);
+                if (c.arena_used + need > p->arena_bytes && !jobs.empty()) break;
+                Job jb{};
+                jb.i = pt.i;
+                jb.j = pt.j;
+                jb.k = pt.k;
+                jb.kfull = std::min(tile_rows(p, pt.i), tile_rows(p, pt.j));
+                double *A = c.alloc((size_t)nb * nb);
+                if (!A || !alloc_job(c, jb, 0)) return TLR_E_NOMEM;
+                jb.A = A;
+                jb.Uout = c.U(pt.i, pt.j);
+                jb.Vout = c.V(pt.i, pt.j);
+                jb.stat = c.tstat(tile_index(pt.i, pt.j));
+                gens.push_back(GenDesc{A, pt.i * nb, pt.j * nb, nb, 0});
+                jobs.push_back(jb);
+                ++pos;
+                if (jobs.size() >= 4096) break;
+            }
+            TLR_PUSH(dg, c, gens);
+            TLR_TRY(gen_tiles_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), mc, s));
+            TLR_TRY(rsvd(c, jobs, tol, nullptr, 0));
+            std::vector<int32_t> st(4 * jobs.size());
+            // gather the per-tile status words
+            for (size_t q = 0; q < jobs.size(); ++q)
+                TLR_HIP(hipMemcpyAsync(&st[4 * q], jobs[q].stat, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            TLR_TRY(c.sync_reset());
+            if (debug_enabled()) {
+                int code = 0;
+                TLR_TRY(c.read_status(&code));
+                for (size_t q = 0; q < jobs.size(); ++q)
+                    std::fprintf(stderr, "compress tile (%d,%d) k=%d write=%d num=%d flag=%d status=%d\n", jobs[q].i,
+                                 jobs[q].j, jobs[q].k, st[4 * q], st[4 * q + 1], st[4 * q + 2], code);
+            }
+            for (size_t q = 0; q < jobs.size(); ++q) {
+                const Job &jb = jobs[q];
+                if (st[4 * q + 2]) {
+                    const int wider = clamp_k(p, 2 * jb.k, jb.kfull);
+                    retry.push_back({jb.i, jb.j, std::max(wider, jb.k)});
+                } else {
+                    const int num = st[4 * q + 1];
+                    ranks[(size_t)jb.i * nt + jb.j] = (num > p->rcap) ? -1 : st[4 * q];
+                }
+            }
+        }
+        pending.swap(retry);
+    }
+    TLR_HIP(hipMemcpyAsync(c.rsig(), ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
+    TLR_HIP(hipMemcpyAsync(c.rL(), ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
+    if (d_ranks)
+        TLR_HIP(hipMemcpyAsync(d_ranks, ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
+    const uint64_t magic = kHintMagic;
+    TLR_HIP(hipMemcpyAsync(&c.pblock()->hint_magic, &magic, sizeof(magic), hipMemcpyHostToDevice, s));
+    TLR_HIP(hipStreamSynchronize(s));
+    return TLR_OK;
+}
+
+// ------------------------------------------------------- factorisation --
+
+tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
+    if (!p || !d_ws) return TLR_E_INVAL;
+    if (ws_bytes < p->ws_bytes) return TLR_E_NOMEM;
+    Ctx c(p, d_ws, s);
+    const int nt = p->nt, nb = p->nb;
+    ParamsBlock hb{};
+    std::vector<int32_t> r((size_t)nt * nt, 0);
+    TLR_HIP(hipMemcpyAsync(&hb, c.pblock(), sizeof(ParamsBlock), hipMemcpyDeviceToHost, s));
+    TLR_HIP(hipMemcpyAsync(r.data(), c.rL(), sizeof(int32_t) * r.size(), hipMemcpyDeviceToHost, s));
+    TLR_HIP(hipStreamSynchronize(s));
+    const double tol = hb.tol;
+    if (hb.dp.status != 0) return TLR_OK;  // already failed: l = -inf
+    for (int i = 0; i < nt; ++i)
+        for (int j = 0; j < i; ++j)
+            if (r[(size_t)i * nt + j] < 0) return TLR_OK;  // overflow recorded by compress
+    std::vector<GemmDesc> hg((size_t)nt * 64 + 64);
+    for (int j = 0; j < nt; ++j) {
+        c.arena_used = 0;
+        int Rj = 0;
+        std::vector<int> off(j + 1, 0);
+        for (int k = 0; k < j; ++k) {
+            off[k] = Rj;
+            Rj += r[(size_t)j * nt + k];
+        }
+        double *Yj = nullptr;
+        if (Rj > 0) {
+            // Yj = [U_j0 | ... | U_j,j-1]; Xd = [U_jk (V_jk^T V_jk)]_k; D_j -= Xd Yj^T
+            Yj = c.alloc((size_t)nb * Rj);
+            double *Xd = c.alloc((size_t)nb * Rj);
+            size_t msz = 0;
+            for (int k = 0; k < j; ++k) msz += (size_t)r[(size_t)j * nt + k] * r[(size_t)j * nt + k];
+            double *Md = c.alloc(std::max<size_t>(msz, 1));
+            if (!Yj || !Xd || !Md) return TLR_E_NOMEM;
+            std::vector<GemmDesc> gm, gx;
+            std::vector<SmallDesc> cp;
+            size_t mo = 0;
+            for (int k = 0; k < j; ++k) {
+                const int rk = r[(size_t)j * nt + k];
+                if (rk == 0) continue;
+                gm.push_back(gd(c.V(j, k), nb, c.V(j, k), nb, Md + mo, rk, rk, rk, nb, 1.0, 0.0));
+                gx.push_back(gd(c.U(j, k), nb, Md + mo, rk, Xd + (size_t)off[k] * nb, nb, nb, rk, rk, 1.0, 0.0));
+                mo += (size_t)rk * rk;
+            }
+            TLR_TRY(launch_gemms(c, true, false, gm));
+            TLR_TRY(launch_gemms(c, false, false, gx));
+            // gather Yj: U_jk occupies the first r_jk columns of its slot (ld nb)
+            std::vector<CopyDesc> cps;
+            int64_t mxw = 0;
+            for (int k = 0; k < j; ++k) {
+                const int rk = r[(size_t)j * nt + k];
+                if (rk == 0) continue;
+                cps.push_back(CopyDesc{c.U(j, k), Yj + (size_t)off[k] * nb, (int64_t)rk * nb});
+                mxw = std::max<int64_t>(mxw, (int64_t)rk * nb);
+            }
+            TLR_PUSH(dcp, c, cps);
+            TLR_TRY(copy_batched(dcp, (int)cps.size(), mxw, s));
+            std::vector<GemmDesc> gdg{gd(Xd, nb, Yj, nb, c.diag(j), nb, nb, nb, Rj, -1.0, 1.0)};
+            TLR_TRY(launch_gemms(c, false, true, gdg));
+        }
+        // dense Cholesky of the updated diagonal tile
+        {
+            std::vector<GemmDesc> pd((size_t)cdiv(nb, 64));
+            potrf_tile_descs(c.diag(j), nb, pd.data());
+            TLR_PUSH(dpd, c, pd);
+            TLR_TRY(potrf_tile(c.diag(j), nb, j, c.params(), dpd, s));
+        }
+        // Schur complement of the tiles below, re-compressed once
+        std::vector<int> rows;
+        for (int i = j + 1; i < nt; ++i) rows.push_back(i);
+        if (Rj > 0 && !rows.empty()) {
+            const size_t mark = c.arena_used;
+            std::vector<int> todo = rows;
+            std::vector<int> kk(nt, 0);
+            for (int i : todo) {
+                const int kfull = std::min(tile_rows(p, i), tile_rows(p, j));
+                kk[i] = clamp_k(p, r[(size_t)i * nt + j] + p->pover, kfull);
+            }
+            while (!todo.empty()) {
+                std::vector<int> retry;
+                size_t pos = 0;
+                while (pos < todo.size()) {
+                    c.arena_used = mark;
+                    std::vector<Job> jobs;
+                    std::vector<GemmDesc> gmm, gxx;
+                    while (pos < todo.size()) {
+                        const int i = todo[pos];
+                        const int rij = r[(size_t)i * nt + j];
+                        const size_t need = (job_words(nb, kk[i], rij, Rj, false) + (size_t)nb * Rj) * sizeof(double);
+                        if (c.arena_used + need > p->arena_bytes && !jobs.empty()) break;
+                        Job jb{};
+                        jb.i = i;
+                        jb.j = j;
+                        jb.k = kk[i];
+                        jb.kfull = std::min(tile_rows(p, i), tile_rows(p, j));
+                        jb.r = rij;
+                        jb.Uop = c.U(i, j);
+                        jb.Vop = c.V(i, j);
+                        double *Xi = c.alloc((size_t)nb * Rj);
+                        if (!Xi || !alloc_job(c, jb, Rj)) return TLR_E_NOMEM;
+                        jb.Xi = Xi;
+                        jb.Uout = c.U(i, j);
+                        jb.Vout = c.V(i, j);
+                        jb.stat = c.tstat(tile_index(i, j));
+                        // X_i blocks: U_ik (V_ik^T V_jk); M_ik in the F buffer's space is
+                        // not free yet, so use the tail of H/T: allocate separately
+                        size_t msz = 0;
+                        for (int k = 0; k < j; ++k) msz += (size_t)r[(size_t)i * nt + k] * r[(size_t)j * nt + k];
+                        double *Mik = c.alloc(std::max<size_t>(msz, 1));
+                        if (!Mik) return TLR_E_NOMEM;
+                        size_t mo = 0;
+                        for (int k = 0; k < j; ++k) {
+                            const int rik = r[(size_t)i * nt + k], rjk = r[(size_t)j * nt + k];
+                            if (rjk == 0) continue;
+                            if (rik == 0) {
+                                // zero block of X_i
+                                gxx.push_back(gd(c.U(i, k), nb, Mik, 1, Xi + (size_t)off[k] * nb, nb, nb, rjk, 0, 1.0, 0.0));
+                                continue;
+                            }
+                            gmm.push_back(gd(c.V(i, k), nb, c.V(j, k), nb, Mik + mo, rik, rik, rjk, nb, 1.0, 0.0));
+                            gxx.push_back(gd(c.U(i, k), nb, Mik + mo, rik, Xi + (size_t)off[k] * nb, nb, nb, rjk, rik,
+                                             1.0, 0.0));
+                            mo += (size_t)rik * rjk;
+                        }
+                        jobs.push_back(jb);
+                        ++pos;
+                        if (jobs.size() >= 4096) break;
+                    }
+                    TLR_TRY(launch_gemms(c, true, false, gmm));
+                    TLR_TRY(launch_gemms(c, false, false, gxx));
+                    TLR_TRY(rsvd(c, jobs, tol, Yj, Rj));
+                    std::vector<int32_t> st(4 * jobs.size());
+                    for (size_t q = 0; q < jobs.size(); ++q)
+                        TLR_HIP(hipMemcpyAsync(&st[4 * q], jobs[q].stat, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                    TLR_TRY(c.sync_reset());
+                    if (debug_enabled()) {
+                        for (size_t q = 0; q < jobs.size(); ++q)
+                            std::fprintf(stderr, "potrf col %d tile (%d,%d) R=%d k=%d r_old=%d write=%d num=%d flag=%d\n", j,
+                                         jobs[q].i, jobs[q].j, Rj, jobs[q].k, jobs[q].r, st[4 * q], st[4 * q + 1],
+                                         st[4 * q + 2]);
+                    }
+                    for (size_t q = 0; q < jobs.size(); ++q) {
+                        const Job &jb = jobs[q];
+                        if (st[4 * q + 2]) {
+                            kk[jb.i] = std::max(clamp_k(p, 2 * jb.k, jb.kfull), jb.k);
+                            retry.push_back(jb.i);
+                        } else {
+                            r[(size_t)jb.i * nt + j] = st[4 * q];
+                        }
+                    }
+                }
+                todo.swap(retry);
+            }
+            c.arena_used = mark;
+        }
+        int code = 0;
+        TLR_TRY(c.read_status(&code));
+        if (code != 0) break;
+        // L_ij = U_ij (L_jj^-1 V_ij)^T
+        std::vector<SmallDesc> sd;
+        int maxc = 0;
+        for (int i : rows) {
+            const int rij = r[(size_t)i * nt + j];
+            if (rij <= 0) continue;
+            SmallDesc d{};
+            d.Y = c.V(i, j);
+            d.ldy = nb;
+            d.k = rij;
+            sd.push_back(d);
+            maxc = std::max(maxc, rij);
+        }
+        if (!sd.empty()) {
+            TLR_PUSH(dsd, c, sd);
+            const size_t nblk = (size_t)cdiv(nb, 64);
+            const size_t need = align_up(sizeof(GemmDesc) * sd.size() * nblk, 256);
+            if (c.desc_used + need > p->desc_bytes) return TLR_E_NOMEM;
+            GemmDesc *dg = reinterpret_cast<GemmDesc *>(c.ws + p->off_desc + c.desc_used);
+            if (hg.size() < sd.size() * nblk) hg.resize(sd.size() * nblk);
+            c.desc_used += need;
+            TLR_TRY(trsm_left_lower(c.diag(j), nb, dsd, sd.data(), (int)sd.size(), maxc, dg, hg.data(), s));
+        }
+        TLR_TRY(c.sync_reset());
+    }
+    TLR_HIP(hipMemcpyAsync(c.rL(), r.data(), sizeof(int32_t) * r.size(), hipMemcpyHostToDevice, s));
+    TLR_HIP(hipStreamSynchronize(s));
+    return TLR_OK;
+}
+
+// --------------------------------------------------------------- solve --
+
+tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_bytes, double *d_out, hipStream_t s) {
+    if (!p || !d_z || !d_ws || !d_out) return TLR_E_INVAL;
+    if (ws_bytes < p->ws_bytes) return TLR_E_NOMEM;
+    Ctx c(p, d_ws, s);
+    const int nt = p->nt, nb = p->nb;
+    TLR_TRY(pad_copy(d_z, p->n, p->npad, c.yvec(), s));
+    const size_t gb = gemv_desc_bytes();
+    std::vector<char> hv(gb * std::max<int64_t>(p->ntiles, 1));
+    std::vector<int> first(nt + 1, 0);
+    size_t cnt = 0;
+    for (int j = 0; j < nt; ++j) {
+        first[j] = (int)cnt;
+        for (int i = j + 1; i < nt; ++i) {
+            make_gemv_desc(hv.data() + gb * cnt, c.U(i, j), c.V(i, j), c.yvec() + (int64_t)j * nb,
+                           c.yvec() + (int64_t)i * nb, c.rL() + (size_t)i * nt + j);
+            ++cnt;
+        }
+    }
+    first[nt] = (int)cnt;
+    char *dv = nullptr;
+    if (cnt > 0) {
+        dv = c.push(hv.data(), gb * cnt);
+        if (!dv) return TLR_E_NOMEM;
+    }
+    for (int j = 0; j < nt; ++j) {
+        TLR_TRY(trsv_tile(c.diag(j), nb, c.yvec() + (int64_t)j * nb, c.params(), s));
+        const int count = first[j + 1] - first[j];
+        if (count > 0) TLR_TRY(lr_gemv(dv + gb * first[j], count, nb, c.params(), s));
+    }
+    TLR_TRY(logdet_quad(c.diag(0), nb, nt, p->n, c.yvec(), c.params(), d_out, s));
+    TLR_HIP(hipStreamSynchronize(s));
+    return TLR_OK;
+}
+
+tlr_status status_read(tlr_plan p, const void *d_ws, tlr_devinfo *out, hipStream_t s) {
+    if (!p || !d_ws || !out) return TLR_E_INVAL;
+    Ctx c(p, const_cast<void *>(d_ws), s);
+    ParamsBlock hb{};
+    std::vector<int32_t> r((size_t)p->nt * p->nt, 0);
+    TLR_HIP(hipStreamSynchronize(s));
+    TLR_HIP(hipMemcpy(&hb, c.pblock(), sizeof(ParamsBlock), hipMemcpyDeviceToHost));
+    TLR_HIP(hipMemcpy(r.data(), c.rL(), sizeof(int32_t) * r.size(), hipMemcpyDeviceToHost));
+    out->code = hb.dp.status;
+    out->tile_i = hb.dp.status ? hb.dp.fail_i : -1;
+    out->tile_j = hb.dp.status ? hb.dp.fail_j : -1;
+    int mx = 0;
+    int64_t sum = 0;
+    for (int i = 0; i < p->nt; ++i)
+        for (int j = 0; j < i; ++j) {
+            mx = std::max(mx, r[(size_t)i * p->nt + j]);
+            sum += std::max(0, r[(size_t)i * p->nt + j]);
+        }
+    out->max_rank = mx;
+    out->rank_sum = sum;
+    return TLR_OK;
+}
+
+}  // namespace tlr
+
+namespace tlr {
+void plan_shape(tlr_plan p, int64_t *n, int32_t *nb, int32_t *nt, int32_t *maxrank) {
+    if (!p) return;
+    if (n) *n = p->n;
+    if (nb) *nb = p->nb;
+    if (nt) *nt = p->nt;
+    if (maxrank) *maxrank = p->rcap;
+}
+}  // namespace tlr
+
+namespace tlr {
+tlr_status tile_read(tlr_plan p, const void *d_ws, int i, int j, double *d_out, int32_t *h_rank, hipStream_t s) {
+    if (!p || !d_ws || !d_out || i < 0 || j < 0 || i >= p->nt || j > i) return TLR_E_INVAL;
+    Ctx c(p, const_cast<void *>(d_ws), s);
+    const int nb = p->nb;
+    if (i == j) {
+        TLR_HIP(hipMemcpyAsync(d_out, c.diag(i), sizeof(double) * nb * nb, hipMemcpyDeviceToDevice, s));
+        TLR_HIP(hipStreamSynchronize(s));
+        if (h_rank) *h_rank = nb;
+        return TLR_OK;
+    }
+    int32_t r = 0;
+    TLR_HIP(hipMemcpyAsync(&r, c.rL() + (size_t)i * p->nt + j, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TLR_HIP(hipStreamSynchronize(s));
+    if (h_rank) *h_rank = r;
+    std::vector<GemmDesc> g{gd(c.U(i, j), nb, c.V(i, j), nb, d_out, nb, nb, nb, std::max(r, 0), 1.0, 0.0)};
+    TLR_TRY(launch_gemms(c, false, true, g));
+    TLR_HIP(hipStreamSynchronize(s));
+    return TLR_OK;
+}
+}  // namespace tlr

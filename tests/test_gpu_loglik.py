@@ -1,0 +1,204 @@
+"""End-to-end parity of the TLR likelihood path against the oracle.
+
+Acceptance bound for FP64 TLR at threshold tol (compression error alone is
+delta_c = l(Sigma~) - l(Sigma), from the oracle):
+    |l_TLR - l_dense| <= max(n * max(1e-8, 0.1 * tol), 10 * |delta_c|)
+and |l_TLR - l_dense| <= 1e-8 * n at tol = 1e-12.  The factor 10 covers the
+single re-compression of each Schur-complement tile, which adds truncation
+error of the same order as the initial compression.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from oracle import likelihood as OL
+from oracle import matern as OM
+from oracle import ordering as OO
+from oracle import tlr as OT
+from paper_2402_09356_amd import binding as B
+from tests.gpu_util import device, from_colmajor, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def bound(n, tol, delta_c):
+    return max(n * max(1e-8, 0.1 * tol), 10 * abs(delta_c))
+
+
+def make_problem(m, theta, kind, cfg=1, locs=None):
+    if locs is None:
+        locs = synthetic.jittered_grid(m, synthetic.seed_for(cfg, synthetic.SEED_LOCS))
+    n = locs.shape[0]
+    e = synthetic.standard_normal(n, synthetic.seed_for(cfg, synthetic.SEED_Z))
+    z = OL.sample_field(locs, theta, e)
+    perm = OO.reorder(locs, kind, seed=synthetic.seed_for(cfg, synthetic.SEED_ORDER))
+    return locs[perm], z[perm]
+
+
+def run_gpu(locs, z, theta, nb, tol, maxrank=0):
+    plan = B.Plan(locs.shape[0], nb, maxrank=maxrank)
+    ws = plan.workspace()
+    dl, dz = to_dev(locs), to_dev(z)
+    ranks = torch.zeros(plan.nt * plan.nt, dtype=torch.int32, device=dl.device)
+    out = plan.loglik(ws, dl, dz, theta, tol, ranks=ranks)
+    torch.cuda.synchronize()
+    return plan, ws, out.cpu().numpy(), ranks.cpu().numpy().reshape(plan.nt, plan.nt)
+
+
+def test_c1_smoke_configuration():
+    """n=1,600 jittered grid, nu=1/2, beta=0.1, Morton, nb=200, tol=1e-9."""
+    device()
+    theta, nb, tol = (1.0, 0.1, 0.5), 200, 1e-9
+    locs, z = make_problem(40, theta, "morton")
+    print("c1 loglik", flush=True)
+    plan, ws, out, ranks = run_gpu(locs, z, theta, nb, tol)
+    dense = OL.loglik_dense(locs, z, theta)
+    comp, oranks = OT.compressed_loglik(locs, z, theta, nb, tol)
+    delta_c = comp.loglik - dense.loglik
+    err = abs(out[2] - dense.loglik)
+    print(f"c1: gpu {out[2]!r} dense {dense.loglik!r} |d|={err:.3e} delta_c={delta_c:.3e}", flush=True)
+    assert np.isfinite(out[2])
+    assert err <= bound(1600, tol, delta_c)
+    assert abs(out[0] - dense.logdet) <= bound(1600, tol, delta_c)
+    # ranks: equal to the exact SVD ranks except inside the tie band
+    sv = OT.tile_svd(OM.covariance_matrix(locs, theta), nb)
+    for (i, j), s in sv.svals.items():
+        exact = OT.numerical_rank(s, tol)
+        if ranks[i, j] != exact:
+            lo, hi = sorted((ranks[i, j], exact))
+            band = s[lo:hi + 1]
+            assert hi - lo <= 1 and np.all(np.abs(band / tol - 1) < 1e-3), (i, j, ranks[i, j], exact)
+
+
+def test_compressed_tiles_and_diagonal_match_oracle():
+    device()
+    theta, nb, tol = (1.0, 0.1, 0.5), 200, 1e-9
+    locs, z = make_problem(40, theta, "hilbert")
+    plan = B.Plan(1600, nb)
+    ws = plan.workspace()
+    plan.gen_tiles(ws, to_dev(locs), theta)
+    sig = OM.covariance_matrix(locs, theta)
+    for k in (0, 3, 7):
+        tile, _ = plan.tile(ws, k, k)
+        ref = sig[k * nb:(k + 1) * nb, k * nb:(k + 1) * nb]
+        np.testing.assert_allclose(tile, ref, rtol=1e-14, atol=1e-300)
+    plan.compress(ws, tol)
+    for (i, j) in [(1, 0), (5, 2), (7, 6), (7, 0)]:
+        tile, r = plan.tile(ws, i, j)
+        ref = sig[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
+        err = np.linalg.norm(tile - ref, 2)
+        s = np.linalg.svd(ref, compute_uv=False)
+        assert err <= 2 * tol + s[r] if r < s.size else 2 * tol, (i, j, r, err)
+
+
+def test_tol_1e12_reaches_dense():
+    device()
+    theta, nb, tol = (1.0, 0.1, 0.5), 200, 1e-12
+    locs, z = make_problem(40, theta, "morton")
+    print("tol 1e-12", flush=True)
+    plan, ws, out, ranks = run_gpu(locs, z, theta, nb, tol, maxrank=nb)
+    dense = OL.loglik_dense(locs, z, theta).loglik
+    print(f"tol12: gpu {out[2]!r} dense {dense!r}", flush=True)
+    assert abs(out[2] - dense) <= 1e-8 * 1600
+
+
+@pytest.mark.parametrize("kind", ["none", "random", "morton", "hilbert", "kdtree"])
+def test_every_ordering_small(kind):
+    device()
+    theta, nb, tol = (1.0, 0.1, 0.5), 100, 1e-9
+    locs, z = make_problem(30, theta, kind)
+    n = locs.shape[0]
+    print(f"ordering {kind}", flush=True)
+    plan, ws, out, ranks = run_gpu(locs, z, theta, nb, tol, maxrank=nb)
+    dense = OL.loglik_dense(locs, z, theta).loglik
+    comp, _ = OT.compressed_loglik(locs, z, theta, nb, tol, maxrank=nb)
+    assert abs(out[2] - dense) <= bound(n, tol, comp.loglik - dense)
+
+
+@pytest.mark.parametrize("nu", [0.8, 1.0, 1.5, 2.5])
+def test_general_smoothness(nu):
+    device()
+    theta, nb, tol = (1.3, 0.07, nu), 128, 1e-9
+    locs, z = make_problem(30, theta, "hilbert")
+    n = locs.shape[0]
+    plan = B.Plan(n, nb)
+    ws = plan.workspace()
+    plan.gen_tiles(ws, to_dev(locs), theta)
+    sig = OM.covariance_matrix(locs, theta)
+    tile, _ = plan.tile(ws, 1, 1)
+    ref = sig[nb:2 * nb, nb:2 * nb]
+    np.testing.assert_allclose(tile, ref, rtol=2e-13, atol=1e-300)
+    print(f"nu={nu}", flush=True)
+    plan2, ws2, out, _ = run_gpu(locs, z, theta, nb, tol, maxrank=nb)
+    dense = OL.loglik_dense(locs, z, theta).loglik
+    comp, _ = OT.compressed_loglik(locs, z, theta, nb, tol, maxrank=nb)
+    assert abs(out[2] - dense) <= bound(n, tol, comp.loglik - dense)
+
+
+def test_ragged_tiles():
+    device()
+    theta, nb, tol = (1.0, 0.05, 0.5), 128, 1e-9
+    locs = synthetic.uniform_points(1000, 77)
+    locs, z = make_problem(0, theta, "kdtree", locs=locs)
+    plan, ws, out, _ = run_gpu(locs, z, theta, nb, tol, maxrank=nb)
+    dense = OL.loglik_dense(locs, z, theta).loglik
+    comp, _ = OT.compressed_loglik(locs, z, theta, nb, tol, maxrank=nb)
+    assert abs(out[2] - dense) <= bound(1000, tol, comp.loglik - dense)
+
+
+def test_deterministic_repeat():
+    device()
+    theta, nb, tol = (1.0, 0.1, 0.5), 200, 1e-9
+    locs, z = make_problem(40, theta, "hilbert")
+    plan = B.Plan(1600, nb)
+    ws = plan.workspace()
+    a = plan.loglik(ws, to_dev(locs), to_dev(z), theta, tol).cpu().numpy()
+    b = plan.loglik(ws, to_dev(locs), to_dev(z), theta, tol).cpu().numpy()
+    ws2 = plan.workspace()
+    c = plan.loglik(ws2, to_dev(locs), to_dev(z), theta, tol).cpu().numpy()
+    # no state is carried between evaluations: bitwise identical results
+    assert a.tobytes() == b.tobytes() == c.tobytes()
+
+
+def test_not_spd_and_rank_overflow_surface_as_minus_inf():
+    device()
+    theta = (1.0, 0.1, 1.5)
+    locs = synthetic.uniform_points(300, 5)
+    locs[10] = locs[11]  # duplicated location: Sigma singular
+    z = synthetic.standard_normal(300, 6)
+    plan, ws, out, _ = run_gpu(locs, z, theta, 64, 1e-9, maxrank=64)
+    assert out[2] == -np.inf
+    assert plan.status(ws)["code"] == 16
+    locs2, z2 = make_problem(20, (1.0, 0.1, 0.5), "random")
+    plan2, ws2, out2, ranks2 = run_gpu(locs2, z2, (1.0, 0.1, 0.5), 100, 1e-9, maxrank=2)
+    assert out2[2] == -np.inf
+    assert plan2.status(ws2)["code"] == 17
+    assert (ranks2[np.tril_indices(4, -1)] == -1).any()
+
+
+def test_collinear_ar1_exact_at_scale():
+    """Points sorted along a line with nu = 1/2: exact l by the Markov
+    factorisation, any n (here 20,000 with nb = 400)."""
+    device()
+    n, nb, tol = 20000, 400, 1e-12
+    locs = synthetic.collinear_points(n, 8)
+    sigma2, beta = 1.0, 0.02
+    e = synthetic.standard_normal(n, 9)
+    t = locs[:, 0] * np.sqrt(2.0)
+    rho = np.exp(-np.diff(t) / beta)
+    var = sigma2 * (1 - rho * rho)
+    # an exact draw from the model by its Markov recursion
+    z = np.empty(n)
+    z[0] = np.sqrt(sigma2) * e[0]
+    for k in range(1, n):
+        z[k] = rho[k - 1] * z[k - 1] + np.sqrt(var[k - 1]) * e[k]
+    r = z[1:] - rho * z[:-1]
+    ref = (-0.5 * np.log(2 * np.pi) - 0.5 * np.log(sigma2) - z[0] ** 2 / (2 * sigma2)
+           + np.sum(-0.5 * np.log(2 * np.pi) - 0.5 * np.log(var) - r * r / (2 * var)))
+    print("ar1 20000", flush=True)
+    plan, ws, out, ranks = run_gpu(locs, z, (sigma2, beta, 0.5), nb, tol)
+    assert abs(out[2] - ref) <= 1e-8 * n
+    # off-diagonal tiles of the exponential kernel on a sorted line have rank 1
+    low = ranks[np.tril_indices(plan.nt, -1)]
+    assert np.all(low <= 1)
