@@ -201,6 +201,38 @@ const char *tlr_strerror(tlr_status code);
 const char *tlr_version(void);
 
 /* ------------------------------------------------------------------------ */
+/* Launch timer                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Per-kernel statistics of the launches made while the timer is on.  Each
+ * instrumented launch is bracketed by two HIP events on the stream it runs
+ * on; `total_ms` sums their elapsed times.  `flops` and `bytes` are the
+ * algorithmic work of the launches whose sizes are known on the host
+ * (`exact_launches`, taking `exact_ms`): operations the method needs, and
+ * each operand read and each result written once in HBM.  Names are kernel
+ * function names as a profiler's kernel trace shows them (template
+ * arguments abbreviated). */
+typedef struct tlr_kstat {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+    int64_t exact_launches;
+    double exact_ms;
+    double flops;
+    double bytes;
+} tlr_kstat;
+
+/* Turn the timer on (nonzero) or off.  Timing adds two event records per
+ * launch; it does not synchronise the stream. */
+tlr_status tlr_kstats_enable(int32_t on);
+/* Wait for pending timed launches, then zero every counter. */
+tlr_status tlr_kstats_reset(void);
+/* Wait for pending timed launches and copy up to `max` entries into `out`
+ * (host array).  Returns the number of kernel classes (may exceed `max`),
+ * or -1 when `out` is null and `max` > 0. */
+int32_t tlr_kstats_read(tlr_kstat *out, int32_t max);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel diagnostics (used by the test suite to check the building blocks)  */
 /* ------------------------------------------------------------------------ */
 
@@ -222,6 +254,21 @@ tlr_status tlr_diag_gemm(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N,
  * Synchronises `stream`. */
 tlr_status tlr_diag_tile(tlr_plan plan, const void *d_ws, int32_t i, int32_t j, double *d_out, int32_t *h_rank,
                          void *stream);
+
+/* Orthonormalise an m x k panel by the CholeskyQR passes of the compression
+ * step (two shifted passes, two deflating passes): on return d_Y holds Q
+ * (m x k, ld m; a zero column marks a direction below rounding) and d_R the
+ * k x k upper-triangular factor with Y_in = Q R.  k <= 512.  d_scratch: at
+ * least 512 + 7*8*k*k bytes.  Synchronises `stream`. */
+tlr_status tlr_diag_cholqr(int32_t m, int32_t k, double *d_Y, double *d_R, void *d_scratch, void *stream);
+
+/* Truncated Householder QR with column pivoting of count k x k matrices:
+ * rank r = first step whose trailing Frobenius norm is <= tol; d_X (count x
+ * k x k) receives Q1 in its first r columns, d_B (count x k x k) receives
+ * B^T (k x r) with A ~ Q1 B.  d_rank: count int32.  d_scratch: at least
+ * 512 + count * (8*k*k + 144) bytes.  Synchronises `stream`. */
+tlr_status tlr_diag_qrcp(int32_t count, int32_t k, const double *d_A, double tol, double *d_X, double *d_B,
+                         int32_t *d_rank, void *d_scratch, void *stream);
 
 /* Singular values (descending) and left singular vectors of k x k matrices
  * by the one-sided Jacobi kernel of the compression step.  d_A: count

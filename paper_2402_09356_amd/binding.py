@@ -33,6 +33,12 @@ class _Theta(ctypes.Structure):
     _fields_ = [("sigma2", ctypes.c_double), ("beta", ctypes.c_double), ("nu", ctypes.c_double)]
 
 
+class KStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("exact_launches", ctypes.c_int64), ("exact_ms", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 class DevInfo(ctypes.Structure):
     _fields_ = [("code", ctypes.c_int32), ("tile_i", ctypes.c_int32), ("tile_j", ctypes.c_int32),
                 ("max_rank", ctypes.c_int32), ("rank_sum", ctypes.c_int64)]
@@ -64,6 +70,11 @@ _SIGNATURES = {
     "tlr_diag_gemm": (I32, [I32, I32, I32, I32, I32, F64, P, I32, P, I32, F64, P, I32, P]),
     "tlr_diag_svd": (I32, [I32, I32, P, F64, P, P, P, P, P]),
     "tlr_diag_tile": (I32, [P, P, I32, I32, P, ctypes.POINTER(I32), P]),
+    "tlr_diag_cholqr": (I32, [I32, I32, P, P, P, P]),
+    "tlr_kstats_enable": (I32, [I32]),
+    "tlr_kstats_reset": (I32, []),
+    "tlr_kstats_read": (I32, [P, I32]),
+    "tlr_diag_qrcp": (I32, [I32, I32, P, F64, P, P, P, P, P]),
 }
 
 
@@ -217,3 +228,48 @@ def diag_svd(mats: torch.Tensor, tol: float):
     _check(lib().tlr_diag_svd(count, k, _ptr(mats), float(tol), _ptr(S), _ptr(X), _ptr(rank), _ptr(scratch),
                               _stream()), "tlr_diag_svd")
     return S, X, rank
+
+
+def diag_cholqr(Y: torch.Tensor):
+    """Y: k x m tensor holding an m x k column-major panel.  Returns (Q, R) as
+    (k x m tensor of Q's column-major data, k x k tensor of R's)."""
+    k, m = Y.shape
+    Q = Y.clone()
+    R = torch.empty(k, k, dtype=torch.float64, device=Y.device)
+    scratch = torch.empty(512 + 7 * 8 * k * k + 4096, dtype=torch.uint8, device=Y.device)
+    _check(lib().tlr_diag_cholqr(m, k, _ptr(Q), _ptr(R), _ptr(scratch), _stream()), "tlr_diag_cholqr")
+    return Q, R
+
+
+def diag_qrcp(mats: torch.Tensor, tol: float):
+    """mats: count x k x k (column-major data).  Returns (X, Bt, rank)."""
+    count, k, _ = mats.shape
+    X = torch.zeros(count, k, k, dtype=torch.float64, device=mats.device)
+    Bt = torch.zeros(count, k, k, dtype=torch.float64, device=mats.device)
+    rank = torch.empty(count, dtype=torch.int32, device=mats.device)
+    scratch = torch.empty(512 + count * (8 * k * k + 144), dtype=torch.uint8, device=mats.device)
+    _check(lib().tlr_diag_qrcp(count, k, _ptr(mats), float(tol), _ptr(X), _ptr(Bt), _ptr(rank), _ptr(scratch),
+                               _stream()), "tlr_diag_qrcp")
+    return X, Bt, rank
+
+
+def kstats_enable(on: bool = True):
+    """Time every instrumented launch with HIP events on its stream."""
+    _check(lib().tlr_kstats_enable(1 if on else 0), "tlr_kstats_enable")
+
+
+def kstats_reset():
+    _check(lib().tlr_kstats_reset(), "tlr_kstats_reset")
+
+
+def kstats() -> list[dict]:
+    """Per-kernel launch statistics, largest total time first."""
+    n = lib().tlr_kstats_read(None, 0)
+    arr = (KStat * max(n, 1))()
+    n = lib().tlr_kstats_read(ctypes.cast(arr, ctypes.c_void_p), n)
+    out = []
+    for k in arr[:n]:
+        out.append({"name": k.name.decode(), "launches": k.launches, "total_ms": k.total_ms,
+                    "exact_launches": k.exact_launches, "exact_ms": k.exact_ms, "flops": k.flops,
+                    "bytes": k.bytes})
+    return sorted(out, key=lambda d: -d["total_ms"])

@@ -1,5 +1,6 @@
 // extern "C" entry points declared in include/tlrmle.h.
 #include "kernels.h"
+#include "ktimer.h"
 
 namespace tlr {
 tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precision prec, uint32_t flags);
@@ -94,6 +95,22 @@ const char *tlr_strerror(tlr_status code) {
 
 const char *tlr_version(void) { return "tlrmle 0.1 (gfx950)"; }
 
+tlr_status tlr_kstats_enable(int32_t on) {
+    tlr::ktimer_enable(on != 0);
+    return TLR_OK;
+}
+
+tlr_status tlr_kstats_reset(void) {
+    tlr::ktimer_reset();
+    return TLR_OK;
+}
+
+int32_t tlr_kstats_read(tlr_kstat *out, int32_t max) {
+    if (max > 0 && !out) return -1;
+    static_assert(sizeof(tlr_kstat) == sizeof(tlr::KStat), "tlr_kstat layout");
+    return tlr::ktimer_read(reinterpret_cast<tlr::KStat *>(out), max < 0 ? 0 : max);
+}
+
 tlr_status tlr_diag_tile(tlr_plan plan, const void *d_ws, int32_t i, int32_t j, double *d_out, int32_t *h_rank,
                          void *stream) {
     return tlr::tile_read(plan, d_ws, i, j, d_out, h_rank, as_stream(stream));
@@ -178,5 +195,101 @@ extern "C" tlr_status tlr_diag_svd(int32_t count, int32_t k, const double *d_A, 
     if (hipStreamSynchronize(s) != hipSuccess) return TLR_E_HIP;
     for (int t = 0; t < count; ++t) hr[t] = hs[4 * t + 1];
     if (hipMemcpy(d_rank, hr.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice) != hipSuccess) return TLR_E_HIP;
+    return TLR_OK;
+}
+
+extern "C" tlr_status tlr_diag_qrcp(int32_t count, int32_t k, const double *d_A, double tol, double *d_X, double *d_B,
+                                    int32_t *d_rank, void *d_scratch, void *stream) {
+    if (count < 0 || k < 1 || k > tlr::kMaxSketch || !d_A || !d_X || !d_B || !d_rank || !d_scratch || !(tol >= 0.0))
+        return TLR_E_INVAL;
+    if (count == 0) return TLR_OK;
+    hipStream_t s = as_stream(stream);
+    char *w = static_cast<char *>(d_scratch);
+    tlr::DevParams *params = reinterpret_cast<tlr::DevParams *>(w);
+    w += 256;
+    double *R = reinterpret_cast<double *>(w);
+    w += sizeof(double) * (size_t)count * k * k;
+    int32_t *stat = reinterpret_cast<int32_t *>(w);
+    w += tlr::align_up(sizeof(int32_t) * 4 * (size_t)count, 256);
+    tlr::SmallDesc *dd = reinterpret_cast<tlr::SmallDesc *>(w);
+    std::vector<tlr::SmallDesc> h(count);
+    for (int t = 0; t < count; ++t) {
+        tlr::SmallDesc d{};
+        d.A = const_cast<double *>(d_A) + (size_t)t * k * k;
+        d.lda = k;
+        d.R = R + (size_t)t * k * k;
+        d.ldr = k;
+        d.X = d_X + (size_t)t * k * k;
+        d.ldx = k;
+        d.Y = d_B + (size_t)t * k * k;
+        d.ldy = k;
+        d.rank = stat + 4 * t;
+        d.flag = stat + 4 * t + 2;
+        d.k = k;
+        d.k_full = k;
+        h[t] = d;
+    }
+    if (hipMemsetAsync(params, 0, sizeof(tlr::DevParams), s) != hipSuccess) return TLR_E_HIP;
+    if (hipMemcpyAsync(dd, h.data(), sizeof(tlr::SmallDesc) * count, hipMemcpyHostToDevice, s) != hipSuccess)
+        return TLR_E_HIP;
+    tlr_status st = tlr::qrcp_trunc(dd, count, k, tol, 0, k, k, params, s);
+    if (st != TLR_OK) return st;
+    std::vector<int32_t> hs(4 * (size_t)count), hr(count);
+    if (hipMemcpyAsync(hs.data(), stat, sizeof(int32_t) * 4 * count, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return TLR_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return TLR_E_HIP;
+    for (int t = 0; t < count; ++t) hr[t] = hs[4 * t];
+    if (hipMemcpy(d_rank, hr.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice) != hipSuccess) return TLR_E_HIP;
+    return TLR_OK;
+}
+
+extern "C" tlr_status tlr_diag_cholqr(int32_t m, int32_t k, double *d_Y, double *d_R, void *d_scratch, void *stream) {
+    if (m < 1 || k < 1 || k > tlr::kMaxSketch || !d_Y || !d_R || !d_scratch) return TLR_E_INVAL;
+    hipStream_t s = as_stream(stream);
+    char *w = static_cast<char *>(d_scratch);
+    tlr::DevParams *params = reinterpret_cast<tlr::DevParams *>(w);
+    w += 256;
+    double *G = reinterpret_cast<double *>(w);
+    double *Rp[4], *T = G + (size_t)k * k;
+    for (int q = 0; q < 4; ++q) Rp[q] = T + (size_t)(q + 1) * k * k;
+    double *T2 = Rp[3] + (size_t)k * k;
+    char *dsc = reinterpret_cast<char *>(T2 + (size_t)k * k);
+    if (hipMemsetAsync(params, 0, sizeof(tlr::DevParams), s) != hipSuccess) return TLR_E_HIP;
+    // descriptors: 4 Gram products, 4 small descs, 3 R products
+    tlr::GemmDesc hg[8];
+    tlr::SmallDesc hsd[4];
+    for (int it = 0; it < 4; ++it) {
+        tlr::GemmDesc g{};
+        g.A = d_Y; g.B = d_Y; g.C = G; g.M = k; g.N = k; g.K = m; g.lda = m; g.ldb = m; g.ldc = k;
+        g.alpha = 1.0; g.beta = 0.0;
+        hg[it] = g;
+        tlr::SmallDesc d{};
+        d.A = G; d.lda = k; d.R = Rp[it]; d.ldr = k; d.Y = d_Y; d.ldy = m; d.m = m; d.k = k;
+        hsd[it] = d;
+    }
+    auto mul = [&](const double *A, const double *B, double *C) {
+        tlr::GemmDesc g{};
+        g.A = A; g.B = B; g.C = C; g.M = k; g.N = k; g.K = k; g.lda = k; g.ldb = k; g.ldc = k;
+        g.alpha = 1.0; g.beta = 0.0;
+        return g;
+    };
+    hg[4] = mul(Rp[3], Rp[2], T);
+    hg[5] = mul(T, Rp[1], T2);
+    hg[6] = mul(T2, Rp[0], d_R);
+    tlr::GemmDesc *dg = reinterpret_cast<tlr::GemmDesc *>(dsc);
+    tlr::SmallDesc *ds = reinterpret_cast<tlr::SmallDesc *>(dsc + tlr::align_up(sizeof(hg), 256));
+    if (hipMemcpyAsync(dg, hg, sizeof(hg), hipMemcpyHostToDevice, s) != hipSuccess) return TLR_E_HIP;
+    if (hipMemcpyAsync(ds, hsd, sizeof(hsd), hipMemcpyHostToDevice, s) != hipSuccess) return TLR_E_HIP;
+    for (int it = 0; it < 4; ++it) {
+        tlr_status st = tlr::gemm_batched(true, false, dg + it, 1, k, k, s);
+        if (st == TLR_OK) st = tlr::chol_small(ds + it, 1, k, it < 2 ? 1 : 2, params, s);
+        if (st == TLR_OK) st = tlr::trsm_rows(ds + it, 1, m, k, s);
+        if (st != TLR_OK) return st;
+    }
+    for (int q = 4; q < 7; ++q) {
+        tlr_status st = tlr::gemm_batched(false, false, dg + q, 1, k, k, s);
+        if (st != TLR_OK) return st;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return TLR_E_HIP;
     return TLR_OK;
 }

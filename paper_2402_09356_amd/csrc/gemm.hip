@@ -8,6 +8,7 @@
 // lies outside their product exit at once, so the grid is sized by the
 // largest product.
 #include "kernels.h"
+#include "ktimer.h"
 
 namespace tlr {
 namespace {
@@ -123,10 +124,23 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *__restrict__ d
 }  // namespace
 
 tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int count, int max_m,
-                        int max_n, hipStream_t s) {
+                        int max_n, hipStream_t s, const GemmDesc *h_descs) {
     if (count <= 0 || max_m <= 0 || max_n <= 0) return TLR_OK;
     const int tiles_m = (int)cdiv(max_m, BM), tiles_n = (int)cdiv(max_n, BN);
     if (count > 65535) return TLR_E_UNSUPPORTED;
+    static const int cls[4] = {ktimer_class("k_gemm_f64<N,N>"), ktimer_class("k_gemm_f64<N,T>"),
+                               ktimer_class("k_gemm_f64<T,N>"), ktimer_class("k_gemm_f64<T,T>")};
+    double flops = 0.0, bytes = 0.0;
+    bool exact = h_descs != nullptr;
+    if (exact && ktimer_on())
+        for (int t = 0; t < count; ++t) {
+            const GemmDesc &g = h_descs[t];
+            if (g.M_dev || g.N_dev || g.K_dev) exact = false;
+            const double M = g.M, N = g.N, K = g.K;
+            flops += 2.0 * M * N * K;
+            bytes += 8.0 * (M * K + K * N + M * N * (g.beta != 0.0 ? 2.0 : 1.0));
+        }
+    KTimer kt(cls[(trans_a ? 2 : 0) + (trans_b ? 1 : 0)], s, flops, bytes, exact);
     const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)count), block(256);
     if (!trans_a && !trans_b)
         hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, block, 0, s, d_descs, tiles_n);

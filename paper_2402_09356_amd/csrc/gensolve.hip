@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "kernels.h"
+#include "ktimer.h"
 
 namespace tlr {
 
@@ -45,7 +46,44 @@ bool make_matern_const(double sigma2, double beta, double nu, MaternConst *out) 
 namespace {
 
 // One work-group per (tile, group of 8 columns): threads run down the rows,
-// so the stores of a column are contiguous.
+// so the stores of a column are contiguous.  KIND is the Matern branch
+// (1: nu=1/2, 2: nu=3/2, 3: nu=5/2, 0: general nu), fixed per instantiation so
+// the closed forms do not carry the register footprint of the K_nu code.
+template <int KIND>
+__device__ inline double matern_kind(double d, const MaternConst &c) {
+    const double x = d / c.beta;
+    if (KIND == 1) return c.sigma2 * exp(-x);
+    if (KIND == 2) return c.sigma2 * (1.0 + x) * exp(-x);
+    if (KIND == 3) return c.sigma2 * (1.0 + x + x * x / 3.0) * exp(-x);
+    if (x == 0.0) return c.sigma2;
+    if (x > kTabXhi) return 0.0;
+    if (x < kTabXlo || c.tab == nullptr) return c.coef * xnu_knu(x, c);
+    return c.coef * xnu_knu_tab(x, c);
+}
+
+// Chebyshev coefficients of h on each piece from its kChebDeg+1 Chebyshev
+// nodes of the first kind (one work-group per piece).
+__global__ __launch_bounds__(64) void k_knu_table(MaternConst c, double *tab) {
+    __shared__ double f[kChebDeg + 1];
+    const int piece = blockIdx.x, j = threadIdx.x;
+    const int n1 = kChebDeg + 1;
+    const double w = 1.0 / c.inv_w;
+    const double mid = c.s_lo + (piece + 0.5) * w, half = 0.5 * w;
+    if (j < n1) {
+        const double t = cos(3.14159265358979323846 * (j + 0.5) / n1);
+        f[j] = log_xnu_knu_scaled(exp(mid + half * t), c);
+    }
+    __syncthreads();
+    if (j < n1) {
+        double acc = 0.0;
+        for (int q = 0; q < n1; ++q) acc += f[q] * cos(3.14159265358979323846 * j * (q + 0.5) / n1);
+        acc *= 2.0 / n1;
+        if (j == 0) acc *= 0.5;
+        tab[piece * n1 + j] = acc;
+    }
+}
+
+template <int KIND>
 __global__ __launch_bounds__(256) void k_gen_tiles(const GenDesc *__restrict__ descs, int nb, int64_t n,
                                                    const double *__restrict__ x, const double *__restrict__ y,
                                                    MaternConst c) {
@@ -65,7 +103,7 @@ __global__ __launch_bounds__(256) void k_gen_tiles(const GenDesc *__restrict__ d
                 v = c.sigma2;
             } else {
                 const double dx = x[gi] - xj, dy = y[gi] - yj;
-                v = matern_cov(sqrt(dx * dx + dy * dy), c);
+                v = matern_kind<KIND>(sqrt(dx * dx + dy * dy), c);
             }
             col[r] = v;
         }
@@ -203,8 +241,30 @@ __global__ __launch_bounds__(1024) void k_logdet_quad(const double *__restrict__
 tlr_status gen_tiles_launch(const GenDesc *d_descs, int count, int nb, int64_t n, const double *x,
                             const double *y, const MaternConst &c, hipStream_t s) {
     if (count <= 0) return TLR_OK;
-    hipLaunchKernelGGL(k_gen_tiles, dim3((unsigned)cdiv(nb, 8), count), dim3(256), 0, s, d_descs, nb, n, x, y, c);
+    static const int cls = ktimer_class("k_gen_tiles");
+    // every tile is written once in full (padding included); the locations
+    // it reads are a rounding error beside that
+    KTimer kt(cls, s, 0.0, 8.0 * (double)nb * nb * count, true);
+    const dim3 grid((unsigned)cdiv(nb, 8), count), block(256);
+    switch (c.kind) {
+        case 1: hipLaunchKernelGGL(k_gen_tiles<1>, grid, block, 0, s, d_descs, nb, n, x, y, c); break;
+        case 2: hipLaunchKernelGGL(k_gen_tiles<2>, grid, block, 0, s, d_descs, nb, n, x, y, c); break;
+        case 3: hipLaunchKernelGGL(k_gen_tiles<3>, grid, block, 0, s, d_descs, nb, n, x, y, c); break;
+        default: hipLaunchKernelGGL(k_gen_tiles<0>, grid, block, 0, s, d_descs, nb, n, x, y, c); break;
+    }
     TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status build_knu_table(MaternConst *c, double *tab, hipStream_t s) {
+    c->tab = nullptr;
+    c->nint = kChebPieces;
+    c->s_lo = std::log(kTabXlo);
+    c->inv_w = kChebPieces / (std::log(kTabXhi) - std::log(kTabXlo));
+    if (c->kind != 0) return TLR_OK;
+    hipLaunchKernelGGL(k_knu_table, dim3(kChebPieces), dim3(64), 0, s, *c, tab);
+    TLR_HIP(hipGetLastError());
+    c->tab = tab;
     return TLR_OK;
 }
 
@@ -228,6 +288,9 @@ tlr_status pad_copy(const double *z, int64_t n, int64_t npad, double *out, hipSt
 }
 
 tlr_status trsv_tile(const double *L, int nb, double *yv, const DevParams *params, hipStream_t s) {
+    static const int cls = ktimer_class("k_trsv_tile");
+    const double b = nb;
+    KTimer kt(cls, s, b * b, 8.0 * (b * (b + 1.0) / 2.0 + 2.0 * b), true);
     hipLaunchKernelGGL(k_trsv_tile, dim3(1), dim3(256), 0, s, L, nb, yv, params);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
@@ -235,6 +298,8 @@ tlr_status trsv_tile(const double *L, int nb, double *yv, const DevParams *param
 
 tlr_status lr_gemv(const void *d_descs, int count, int nb, const DevParams *params, hipStream_t s) {
     if (count <= 0) return TLR_OK;
+    static const int cls = ktimer_class("k_lr_gemv");
+    KTimer kt(cls, s, 0.0, 0.0, false);  // ranks live in the descriptors on the device
     hipLaunchKernelGGL(k_lr_gemv, dim3(count), dim3(256), 0, s, static_cast<const GemvDesc *>(d_descs), nb,
                        params);
     TLR_HIP(hipGetLastError());

@@ -24,8 +24,10 @@ struct GemmDesc {
 
 // trans_a / trans_b: op(X) = X^T.  max_m, max_n bound every product's M, N
 // (they size the grid; products smaller than the bound exit early).
+// h_descs: optional host copy of the descriptors, used only to count the
+// launch's work for the launch timer.
 tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int count, int max_m,
-                        int max_n, hipStream_t s);
+                        int max_n, hipStream_t s, const GemmDesc *h_descs = nullptr);
 
 // Small dense problems, one work-group each.
 struct SmallDesc {
@@ -46,9 +48,10 @@ struct SmallDesc {
 // k(k+1)) u trace(A); mode 2: no shift, pivots below 1e-12 max diag(A) deflate
 // their column; mode 0: plain.  A is read-only.
 tlr_status chol_small(const SmallDesc *d_descs, int count, int max_k, int mode, DevParams *params,
-                      hipStream_t s);
+                      hipStream_t s, const SmallDesc *h_descs = nullptr);
 // Y <- Y R^-1 (R upper triangular k x k), in place, row by row.
-tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, hipStream_t s);
+tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, hipStream_t s,
+                     const SmallDesc *h_descs = nullptr);
 // Largest sketch width any kernel accepts.
 constexpr int kMaxSketch = 512;
 
@@ -58,6 +61,13 @@ constexpr int kMaxSketch = 512;
 // and k < k_full (the sample was too narrow to resolve the threshold).
 tlr_status jacobi_svd(const SmallDesc *d_descs, int count, int max_k, double tol, int min_tail,
                       int k_full, int rank_cap, DevParams *params, hipStream_t s);
+
+// Truncated Householder QR with column pivoting of A (k x k): rank r is the
+// first step whose trailing Frobenius norm is <= tol; X = Q1 (k x r),
+// Y = B^T (k x r) with A ~ Q1 B; R = k x k scratch (when k is too large for LDS).
+// flag = 1 (rank 0 written) when k - r < min_tail and k < k_full.
+tlr_status qrcp_trunc(const SmallDesc *d_descs, int count, int max_k, double tol, int min_tail, int k_full,
+                      int rank_cap, DevParams *params, hipStream_t s);
 
 // Dense diagonal-tile kernels (nb x nb, column-major, ld = nb).
 // Blocked Cholesky (block 64): the trailing updates use ceil(nb/64) GEMM
@@ -86,6 +96,10 @@ struct GenDesc {
 };
 tlr_status gen_tiles_launch(const GenDesc *d_descs, int count, int nb, int64_t n, const double *x,
                             const double *y, const MaternConst &c, hipStream_t s);
+
+// Per-theta table for general nu (kChebPieces * (kChebDeg+1) doubles at tab);
+// sets c->tab (left null for the closed forms).
+tlr_status build_knu_table(MaternConst *c, double *tab, hipStream_t s);
 
 // Misc.
 tlr_status gaussian_fill(double *out, int64_t count, uint64_t seed, hipStream_t s);

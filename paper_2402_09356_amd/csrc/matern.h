@@ -31,7 +31,17 @@ struct MaternConst {
     double fact;    // mu pi / sin(mu pi), 1 at mu = 0
     int N;          // number of upward recurrence steps
     int kind;       // 0 general, 1 nu=1/2, 2 nu=3/2, 3 nu=5/2
+    // general nu: piecewise Chebyshev table of h(s) = log(x^nu K_nu(x)) + x,
+    // s = log x, on [s_lo, s_lo + nint / inv_w], kChebDeg+1 coefficients per piece
+    const double *tab;
+    double s_lo, inv_w;
+    int nint;
 };
+
+constexpr int kChebDeg = 10;
+constexpr int kChebPieces = 160;
+constexpr double kTabXlo = 1e-6;
+constexpr double kTabXhi = 745.0;
 
 // Host: constants of one theta.  Returns false for invalid theta.
 bool make_matern_const(double sigma2, double beta, double nu, MaternConst *out);
@@ -89,6 +99,32 @@ __device__ inline double xnu_knu(double x, const MaternConst &c) {
         k1 = k2;
     }
     return pow(x, c.nu) * k0;
+}
+
+// h(s) = log(x^nu K_nu(x)) + x by the accurate evaluator (table nodes).
+__device__ inline double log_xnu_knu_scaled(double x, const MaternConst &c) {
+    if (x >= 2.0) return c.nu * log(x) + log(scaled_k_integral(c.nu, x));
+    return log(xnu_knu(x, c)) + x;
+}
+
+// x^nu K_nu(x) from the table (x in [kTabXlo, kTabXhi]).
+__device__ inline double xnu_knu_tab(double x, const MaternConst &c) {
+    const double u = (log(x) - c.s_lo) * c.inv_w;
+    int idx = (int)u;
+    idx = idx < 0 ? 0 : (idx >= c.nint ? c.nint - 1 : idx);
+    const double t = 2.0 * (u - (double)idx) - 1.0;
+    const double *cf = c.tab + idx * (kChebDeg + 1);
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int m = kChebDeg; m >= 1; --m) {
+        const double b0 = cf[m] + 2.0 * t * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    const double h = cf[0] + t * b1 - b2;
+    // exp(h) exp(-x): each factor keeps its own relative accuracy, unlike
+    // exp(h - x) whose large argument carries |h - x| ulp of rounding
+    return (x < 700.0) ? exp(h) * exp(-x) : exp(h - x);
 }
 
 __device__ inline double matern_cov(double d, const MaternConst &c) {

@@ -8,6 +8,7 @@
 #include <cmath>
 
 #include "kernels.h"
+#include "ktimer.h"
 
 namespace tlr {
 namespace {
@@ -15,6 +16,10 @@ namespace {
 constexpr int kSmallThreads = 256;
 constexpr int kLdsK = 124;  // k x k float64 (plus small arrays) fits in LDS up to this k
 constexpr int kJacK = 112;  // Jacobi working copy k x (k+1) plus partial sums
+constexpr int kPackK = 176; // packed lower triangle k(k+1)/2 <= kLdsK^2 doubles
+constexpr int kRegK = 176;  // register-resident pivoted QR (one column per thread)
+constexpr int kCholLds = (kLdsK * kLdsK > kPackK * (kPackK + 1) / 2) ? kLdsK * kLdsK : kPackK * (kPackK + 1) / 2;
+static_assert(kPackK * (kPackK + 1) / 2 <= kCholLds, "packed Cholesky must fit its LDS array");
 
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -85,9 +90,92 @@ __device__ bool chol_inplace(double *W, int ld, int k, double defl, double *part
     return true;
 }
 
+// Cholesky of W (k x k, global, ld) in 64-wide blocks, right-looking: the
+// diagonal block is factored in LDS, the panel below is solved row by row
+// against it in place, and the trailing lower triangle is updated from the
+// panel (all in global memory, which stays in L2 at these sizes).  For k too
+// large to hold W in LDS.  Same deflation rule as chol_inplace.
+__device__ bool chol_blocked_global(double *W, int ld, int k, double defl, double *Lb, double *part, int *s_fail) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int b0 = 0; b0 < k; b0 += 64) {
+        const int bs = (k - b0 < 64) ? k - b0 : 64;
+        for (int e = tid; e < 64 * 64; e += nt) {
+            const int r = e & 63, q = e >> 6;
+            Lb[e] = (r < bs && q < bs) ? W[(b0 + r) + (int64_t)(b0 + q) * ld] : 0.0;
+        }
+        __syncthreads();
+        if (!chol_inplace(Lb, 64, bs, defl, part, s_fail)) return false;
+        for (int e = tid; e < 64 * 64; e += nt) {
+            const int r = e & 63, q = e >> 6;
+            if (r < bs && q < bs && r >= q) W[(b0 + r) + (int64_t)(b0 + q) * ld] = Lb[r + q * 64];
+        }
+        const int rest = k - b0 - bs;
+        if (rest <= 0) break;
+        // panel rows: x L_bb^T = a  (a dead diagonal gives a zero entry)
+        for (int rr = tid; rr < rest; rr += nt) {
+            double *wr = W + (b0 + bs + rr) + (int64_t)b0 * ld;
+            for (int cc = 0; cc < bs; ++cc) {
+                double a = wr[(int64_t)cc * ld];
+                for (int cp = 0; cp < cc; ++cp) a -= wr[(int64_t)cp * ld] * Lb[cc + cp * 64];
+                const double dg = Lb[cc + cc * 64];
+                wr[(int64_t)cc * ld] = (dg != 0.0) ? a / dg : 0.0;
+            }
+        }
+        __syncthreads();
+        // trailing lower triangle: W[r][q] -= sum_c P[r][c] P[q][c]
+        for (int e = tid; e < rest * rest; e += nt) {
+            const int rr = e % rest, qq = e / rest;
+            if (rr < qq) continue;
+            const double *pr = W + (b0 + bs + rr) + (int64_t)b0 * ld;
+            const double *pq = W + (b0 + bs + qq) + (int64_t)b0 * ld;
+            double acc = 0.0;
+            for (int cc = 0; cc < bs; ++cc) acc += pr[(int64_t)cc * ld] * pq[(int64_t)cc * ld];
+            W[(b0 + bs + rr) + (int64_t)(b0 + bs + qq) * ld] -= acc;
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// Lower Cholesky with the lower triangle packed by columns in LDS: (r, q),
+// r >= q, at q*k - q(q-1)/2 + (r - q).  Same algorithm and deflation rule as
+// chol_inplace; lets k up to kPackK stay on chip.
+__device__ inline int pk(int r, int q, int k) { return q * k - (q * (q - 1)) / 2 + (r - q); }
+
+__device__ bool chol_packed(double *P, int k, double defl, double *part, int *s_fail) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int half = nt >> 1;
+    const int side = tid / half, lt = tid - side * half;
+    for (int c = 0; c < k; ++c) {
+        const int qs = side ? (c >> 1) : 0, qe = side ? c : (c >> 1);
+        for (int r = c + lt; r < k; r += half) {
+            double acc = 0.0;
+            for (int q = qs; q < qe; ++q) acc += P[pk(r, q, k)] * P[pk(c, q, k)];
+            part[r + side * kMaxSketch] = acc;
+        }
+        __syncthreads();
+        for (int r = c + tid; r < k; r += nt) part[r] = P[pk(r, c, k)] - part[r] - part[r + kMaxSketch];
+        __syncthreads();
+        const double piv = part[c];
+        if (!isfinite(piv) || (defl == 0.0 && !(piv > 0.0))) {
+            if (tid == 0) *s_fail = c + 1;
+            __syncthreads();
+            return false;
+        }
+        if (defl > 0.0 && piv <= defl) {
+            for (int r = c + tid; r < k; r += nt) P[pk(r, c, k)] = 0.0;
+        } else {
+            const double inv = 1.0 / sqrt(piv);
+            for (int r = c + tid; r < k; r += nt) P[pk(r, c, k)] = (r == c) ? sqrt(piv) : part[r] * inv;
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
 __global__ __launch_bounds__(kSmallThreads) void k_chol_small(const SmallDesc *__restrict__ descs,
                                                                int mode, DevParams *params) {
-    __shared__ double lds[kLdsK * kLdsK];
+    __shared__ double lds[kCholLds];
     __shared__ double part[2 * kMaxSketch];
     __shared__ double red[kSmallThreads / 64];
     __shared__ int s_fail;
@@ -95,6 +183,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_small(const SmallDesc *_
     const int k = d.k_dev ? *d.k_dev : d.k;
     if (k <= 0) return;
     const int tid = threadIdx.x;
+    const bool packed = (k > kLdsK) && (k <= kPackK);
     double *W = (k <= kLdsK) ? lds : d.R;
     const int ldw = (k <= kLdsK) ? k : d.ldr;
     // mode 1: shifted (shift = 11 (m k + k (k+1)) u ||Y||^2, the squared norm
@@ -113,12 +202,33 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_small(const SmallDesc *_
         mx = block_max(mx, red);
         defl = (mx > 0.0) ? 1e-12 * mx : 1e-300;
     }
-    for (int e = tid; e < k * k; e += blockDim.x) {
-        const int r = e % k, q = e / k;
-        if (r >= q) W[r + q * ldw] = d.A[r + (int64_t)q * d.lda] + ((r == q) ? shift : 0.0);
+    if (packed) {
+        for (int q = 0; q < k; ++q)
+            for (int r = q + tid; r < k; r += blockDim.x)
+                lds[pk(r, q, k)] = d.A[r + (int64_t)q * d.lda] + ((r == q) ? shift : 0.0);
+    } else {
+        for (int e = tid; e < k * k; e += blockDim.x) {
+            const int r = e % k, q = e / k;
+            if (r >= q) W[r + q * ldw] = d.A[r + (int64_t)q * d.lda] + ((r == q) ? shift : 0.0);
+        }
     }
     __syncthreads();
-    const bool ok = chol_inplace(W, ldw, k, defl, part, &s_fail);
+    bool ok;
+    if (packed) {
+        ok = chol_packed(lds, k, defl, part, &s_fail);
+        if (ok) {
+            for (int e = tid; e < k * k; e += blockDim.x) {
+                const int r = e % k, q = e / k;
+                d.R[r + (int64_t)q * d.ldr] = (r <= q) ? lds[pk(q, r, k)] : 0.0;
+            }
+            return;
+        }
+    } else if (k <= kLdsK) {
+        ok = chol_inplace(W, ldw, k, defl, part, &s_fail);
+    } else {
+        __syncthreads();
+        ok = chol_blocked_global(W, ldw, k, defl, lds, part, &s_fail);
+    }
     if (!ok) {
         if (tid == 0) set_status(params, TLR_NOT_SPD, -100 - d.tile_i, -100 - d.tile_j);
         // leave an identity factor so downstream arithmetic stays finite
@@ -158,42 +268,55 @@ __global__ __launch_bounds__(kSmallThreads) void k_chol_small(const SmallDesc *_
 // substitution of its row, 8 columns at a time in registers.  R is read with
 // wave-uniform addresses.  Panels wider than kTrsmLds columns stay in global
 // memory (same arithmetic).
-constexpr int kTrsmLds = 240;
+constexpr int kTrsmLds = 176;
 
-template <bool LDS>
-__device__ void row_solve(double *yrow, int64_t stride, int k, const double *__restrict__ R, int64_t ldr) {
-    constexpr int CH = 8;
+// Forward substitution of one row y against upper-triangular R, CH columns
+// at a time; the block R[0:c0+CH, c0:c0+CH] is staged in LDS by the whole
+// work-group (one wave) so the inner loop reads it as a broadcast.
+constexpr int kTrsmCh = 8;
+__device__ void row_solve(double *yrow, int64_t stride, int k, const double *__restrict__ R, int64_t ldr,
+                          double *Rb, bool valid) {
+    constexpr int CH = kTrsmCh;
+    const int t = threadIdx.x;
     for (int c0 = 0; c0 < k; c0 += CH) {
         const int cw = (k - c0 < CH) ? (k - c0) : CH;
+        const int rows = c0 + cw;
+        __syncthreads();
+        for (int e = t; e < rows * CH; e += blockDim.x) {
+            const int q = e / CH, j = e - q * CH;
+            Rb[e] = (j < cw) ? R[q + (int64_t)(c0 + j) * ldr] : 0.0;
+        }
+        __syncthreads();
+        if (!valid) continue;
         double acc[CH];
 #pragma unroll
-        for (int t = 0; t < CH; ++t) acc[t] = (t < cw) ? yrow[(c0 + t) * stride] : 0.0;
+        for (int j = 0; j < CH; ++j) acc[j] = (j < cw) ? yrow[(c0 + j) * stride] : 0.0;
         for (int q = 0; q < c0; ++q) {
             const double v = yrow[q * stride];
-            const double *rq = R + q + c0 * ldr;
+            const double *rq = Rb + q * CH;
 #pragma unroll
-            for (int t = 0; t < CH; ++t)
-                if (t < cw) acc[t] -= v * rq[t * ldr];
+            for (int j = 0; j < CH; ++j) acc[j] -= v * rq[j];
         }
 #pragma unroll
-        for (int t = 0; t < CH; ++t) {
-            if (t < cw) {
-                double a = acc[t];
+        for (int j = 0; j < CH; ++j) {
+            if (j < cw) {
+                double a = acc[j];
 #pragma unroll
-                for (int tp = 0; tp < CH; ++tp)
-                    if (tp < t) a -= acc[tp] * R[(c0 + tp) + (c0 + t) * ldr];
-                const double rd = R[(c0 + t) + (c0 + t) * ldr];
-                acc[t] = (rd != 0.0) ? a / rd : 0.0;  // zero diagonal: dead direction
+                for (int jp = 0; jp < CH; ++jp)
+                    if (jp < j) a -= acc[jp] * Rb[(c0 + jp) * CH + j];
+                const double rd = Rb[(c0 + j) * CH + j];
+                acc[j] = (rd != 0.0) ? a / rd : 0.0;  // zero diagonal: dead direction
             }
         }
 #pragma unroll
-        for (int t = 0; t < CH; ++t)
-            if (t < cw) yrow[(c0 + t) * stride] = acc[t];
+        for (int j = 0; j < CH; ++j)
+            if (j < cw) yrow[(c0 + j) * stride] = acc[j];
     }
 }
 
 __global__ __launch_bounds__(64) void k_trsm_rows(const SmallDesc *__restrict__ descs) {
     __shared__ double Yt[kTrsmLds * 64];
+    __shared__ double Rb[kMaxSketch * kTrsmCh];
     const SmallDesc d = descs[blockIdx.y];
     const int k = d.k_dev ? *d.k_dev : d.k;
     const int r0 = blockIdx.x * 64;
@@ -204,11 +327,11 @@ __global__ __launch_bounds__(64) void k_trsm_rows(const SmallDesc *__restrict__ 
     const int64_t ldy = d.ldy;
     if (k <= kTrsmLds) {
         for (int c = 0; c < k; ++c) Yt[c * 64 + t] = valid ? d.Y[row + c * ldy] : 0.0;
-        row_solve<true>(Yt + t, 64, k, d.R, d.ldr);
+        row_solve(Yt + t, 64, k, d.R, d.ldr, Rb, true);
         if (valid)
             for (int c = 0; c < k; ++c) d.Y[row + c * ldy] = Yt[c * 64 + t];
-    } else if (valid) {
-        row_solve<false>(d.Y + row, ldy, k, d.R, d.ldr);
+    } else {
+        row_solve(d.Y + (valid ? row : 0), ldy, k, d.R, d.ldr, Rb, valid);
     }
 }
 
@@ -365,6 +488,392 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi_svd(const SmallDesc *_
     }
 }
 
+// --------------------------------------------- truncated pivoted QR --
+
+// Householder QR with column pivoting of A (k x k), stopped at the first step
+// c where the Frobenius norm of the trailing block is <= tol:
+//     A Pi = Q [R11 R12; 0 R22],  ||R22||_F <= tol,
+// so A ~ Q1 B with Q1 = Q[:, :r] (k x r, orthonormal) and B = [R11 R12] Pi^T
+// (r x k), spectral error <= tol.  Outputs: X = Q1 (ldx), Y = B^T (k x r, ldy),
+// rank = {r, r}, flag = 0 (a rank above rank_cap sets TLR_RANK_OVERFLOW and
+// is capped).  The working copy is row-major (element (i, j) at i*ld + j) so
+// that the thread owning column j and its neighbours touch consecutive words.
+template <int THREADS>
+__device__ void qrcp_trunc(double *M, int ld, int k, double tol2, double *cn, double *beta, int *perm,
+                           double *red, int *ired, int *s_r) {
+    const int tid = threadIdx.x;
+    for (int j = tid; j < k; j += THREADS) {
+        double s2 = 0.0;
+        for (int i = 0; i < k; ++i) s2 += M[i * ld + j] * M[i * ld + j];
+        cn[j] = s2;
+        perm[j] = j;
+    }
+    __syncthreads();
+    int c = 0;
+    for (; c < k; ++c) {
+        // trailing Frobenius^2 and pivot (largest norm, smallest index on ties)
+        double rem = 0.0, best = -1.0;
+        int bj = c;
+        for (int j = c + tid; j < k; j += THREADS) {
+            rem += cn[j];
+            if (cn[j] > best) { best = cn[j]; bj = j; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            rem += __shfl_xor(rem, off, 64);
+            const double ob = __shfl_xor(best, off, 64);
+            const int oj = __shfl_xor(bj, off, 64);
+            if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+        }
+        const int lane = tid & 63, wave = tid >> 6;
+        if (lane == 0) { red[wave] = rem; red[8 + wave] = best; ired[wave] = bj; }
+        __syncthreads();
+        rem = 0.0; best = -1.0; bj = c;
+        for (int w = 0; w < THREADS / 64; ++w) {
+            rem += red[w];
+            if (red[8 + w] > best || (red[8 + w] == best && ired[w] < bj)) { best = red[8 + w]; bj = ired[w]; }
+        }
+        if (rem <= tol2) break;
+        __syncthreads();
+        if (bj != c) {  // swap columns c and bj (all rows), norms and permutation
+            for (int i = tid; i < k; i += THREADS) {
+                const double t = M[i * ld + c];
+                M[i * ld + c] = M[i * ld + bj];
+                M[i * ld + bj] = t;
+            }
+            if (tid == 0) {
+                const double t = cn[c]; cn[c] = cn[bj]; cn[bj] = t;
+                const int q = perm[c]; perm[c] = perm[bj]; perm[bj] = q;
+            }
+        }
+        __syncthreads();
+        // Householder vector of M[c:, c]: v = x - alpha e1, beta = 2 / v^T v
+        double x2 = 0.0;
+        for (int i = c + 1 + tid; i < k; i += THREADS) x2 += M[i * ld + c] * M[i * ld + c];
+        for (int off = 32; off > 0; off >>= 1) x2 += __shfl_xor(x2, off, 64);
+        if (lane == 0) red[16 + wave] = x2;
+        __syncthreads();
+        x2 = 0.0;
+        for (int w = 0; w < THREADS / 64; ++w) x2 += red[16 + w];
+        const double x0 = M[c * ld + c];
+        const double nrm = sqrt(x0 * x0 + x2);
+        const double alpha = (x0 > 0.0) ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        const double vtv = v0 * v0 + x2;
+        const double bta = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+        __syncthreads();
+        if (tid == 0) {
+            M[c * ld + c] = v0;  // v stored in column c rows c..k-1 until the end
+            beta[c] = bta;
+        }
+        __syncthreads();
+        // apply to the trailing columns and refresh their norms
+        for (int j = c + 1 + tid; j < k; j += THREADS) {
+            double w = 0.0;
+            for (int i = c; i < k; ++i) w += M[i * ld + c] * M[i * ld + j];
+            w *= bta;
+            double s2 = 0.0;
+            for (int i = c; i < k; ++i) {
+                const double nv = M[i * ld + j] - w * M[i * ld + c];
+                M[i * ld + j] = nv;
+                if (i > c) s2 += nv * nv;
+            }
+            cn[j] = s2;
+        }
+        __syncthreads();
+        if (tid == 0) red[24] = alpha;
+        __syncthreads();
+        // keep alpha (the R diagonal) aside: column c below the diagonal holds v
+        if (tid == 0) cn[c] = red[24];
+        __syncthreads();
+    }
+    if (tid == 0) *s_r = c;
+    __syncthreads();
+}
+
+// Register-resident variant for kJacK < k <= S*KH, 256*S threads: column j
+// is held in registers by threads j + 256 h, h = 0..S-1, each owning rows
+// [h KH, (h+1) KH); loops are fully unrolled with the row range as a predicate
+// so the arrays stay in VGPRs.  Partial dot products / norms of the S parts
+// meet in LDS.  Same arithmetic as qrcp_trunc.  vstore: k x k global scratch
+// holding the reflectors.
+template <int KH, int S>
+__device__ void qrcp_reg(const SmallDesc &d, int k, double tol2, int min_tail, int k_full, int rank_cap,
+                         DevParams *params, double *vstore) {
+    __shared__ double sv[S * KH];
+    __shared__ double part[S][256], part2[S][256];
+    __shared__ double cn[256];
+    __shared__ double beta[S * KH];
+    __shared__ double alph[S * KH];
+    __shared__ int perm[256];
+    __shared__ double red[24];
+    __shared__ int ired[8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = tid & 255, h = tid >> 8, row0 = h * KH;
+    const bool own = j < k;
+    double col[KH];
+#pragma unroll
+    for (int ii = 0; ii < KH; ++ii)
+        col[ii] = (own && row0 + ii < k) ? d.A[(row0 + ii) + (int64_t)j * d.lda] : 0.0;
+    {
+        double s2 = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < KH; ++ii) s2 += col[ii] * col[ii];
+        part[h][j] = s2;
+    }
+    __syncthreads();
+    if (h == 0) {
+        double t = 0.0;
+        for (int q = 0; q < S; ++q) t += part[q][j];
+        cn[j] = own ? t : -1.0;
+        perm[j] = j;
+    }
+    __syncthreads();
+    int c = 0;
+    for (; c < k; ++c) {
+        if (h == 0) {
+            const bool act = own && j >= c;
+            double rem = act ? cn[j] : 0.0, best = act ? cn[j] : -1.0;
+            int bj = act ? j : k;
+            for (int off = 32; off > 0; off >>= 1) {
+                rem += __shfl_xor(rem, off, 64);
+                const double ob = __shfl_xor(best, off, 64);
+                const int oj = __shfl_xor(bj, off, 64);
+                if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+            }
+            if (lane == 0) { red[wave] = rem; red[8 + wave] = best; ired[wave] = bj; }
+        }
+        __syncthreads();
+        double rem = 0.0, best = -1.0;
+        int bj = k;
+        for (int w = 0; w < 4; ++w) {
+            rem += red[w];
+            if (red[8 + w] > best || (red[8 + w] == best && ired[w] < bj)) { best = red[8 + w]; bj = ired[w]; }
+        }
+        if (rem <= tol2) break;
+        __syncthreads();
+        if (bj != c) {  // swap columns c and bj through LDS, both halves
+            if (j == bj) {
+#pragma unroll
+                for (int ii = 0; ii < KH; ++ii) sv[row0 + ii] = col[ii];
+            }
+            __syncthreads();
+            if (j == c) {
+#pragma unroll
+                for (int ii = 0; ii < KH; ++ii) {
+                    const double t = col[ii];
+                    col[ii] = sv[row0 + ii];
+                    sv[row0 + ii] = t;
+                }
+            }
+            __syncthreads();
+            if (j == bj) {
+#pragma unroll
+                for (int ii = 0; ii < KH; ++ii) col[ii] = sv[row0 + ii];
+            }
+            if (tid == 0) {
+                const double t = cn[c]; cn[c] = cn[bj]; cn[bj] = t;
+                const int q = perm[c]; perm[c] = perm[bj]; perm[bj] = q;
+            }
+            __syncthreads();
+        }
+        // Householder vector of column c: partial sums of both halves
+        if (j == c) {
+            double x2 = 0.0, x0 = 0.0;
+#pragma unroll
+            for (int ii = 0; ii < KH; ++ii) {
+                const int i = row0 + ii;
+                if (i == c) x0 = col[ii];
+                if (i > c) x2 += col[ii] * col[ii];
+            }
+            part[h][0] = x2;
+            part2[h][0] = x0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double x2 = 0.0, x0 = 0.0;
+            for (int q = 0; q < S; ++q) {
+                x2 += part[q][0];
+                x0 += part2[q][0];
+            }
+            const double nrm = sqrt(x0 * x0 + x2);
+            const double alpha = (x0 > 0.0) ? -nrm : nrm;
+            const double v0 = x0 - alpha;
+            const double vtv = v0 * v0 + x2;
+            beta[c] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+            alph[c] = alpha;
+            red[16] = v0;
+        }
+        __syncthreads();
+        if (j == c) {
+            const double v0 = red[16];
+#pragma unroll
+            for (int ii = 0; ii < KH; ++ii) {
+                const int i = row0 + ii;
+                const double vi = (i < c) ? 0.0 : (i == c ? v0 : col[ii]);
+                sv[i] = vi;
+                if (i < k) vstore[i + (int64_t)c * k] = vi;
+            }
+        }
+        __syncthreads();
+        const bool upd = own && j > c;
+        if (upd) {
+            double w = 0.0;
+#pragma unroll
+            for (int ii = 0; ii < KH; ++ii) w += sv[row0 + ii] * col[ii];
+            part[h][j] = w;
+        }
+        __syncthreads();
+        if (upd) {
+            double w = 0.0;
+            for (int q = 0; q < S; ++q) w += part[q][j];
+            w *= beta[c];
+            double s2 = 0.0;
+#pragma unroll
+            for (int ii = 0; ii < KH; ++ii) {
+                col[ii] -= w * sv[row0 + ii];
+                if (row0 + ii > c) s2 += col[ii] * col[ii];
+            }
+            part2[h][j] = s2;
+        }
+        __syncthreads();
+        if (h == 0 && upd) {
+            double t = 0.0;
+            for (int q = 0; q < S; ++q) t += part2[q][j];
+            cn[j] = t;
+        }
+        __syncthreads();
+    }
+    const int rr = c;
+    const int insufficient = (k - rr < min_tail) && (k < (d.k_full < k_full ? d.k_full : k_full));
+    int r = insufficient ? 0 : rr;
+    if (!insufficient && r > rank_cap) {
+        if (tid == 0) set_status(params, TLR_RANK_OVERFLOW, d.tile_i, d.tile_j);
+        r = rank_cap;
+    }
+    // B^T: column j of R (rows < r) goes to Y[perm[j], :]
+    if (own) {
+#pragma unroll
+        for (int ii = 0; ii < KH; ++ii) {
+            const int i = row0 + ii;
+            if (i < r) {
+                const double v = (i < j) ? col[ii] : (i == j ? alph[i] : 0.0);
+                d.Y[perm[j] + (int64_t)i * d.ldy] = v;
+            }
+        }
+    }
+    // Q1 = H_0 ... H_{r-1} [I_r; 0]: column q in the registers of threads q, q+256
+    double qc[KH];
+#pragma unroll
+    for (int ii = 0; ii < KH; ++ii) qc[ii] = (row0 + ii == j) ? 1.0 : 0.0;
+    for (int cc = r - 1; cc >= 0; --cc) {
+        __syncthreads();
+        for (int i = tid; i < S * KH; i += 256 * S) sv[i] = (i < k) ? vstore[i + (int64_t)cc * k] : 0.0;
+        __syncthreads();
+        if (j < r) {
+            double w = 0.0;
+#pragma unroll
+            for (int ii = 0; ii < KH; ++ii) w += sv[row0 + ii] * qc[ii];
+            part[h][j] = w;
+        }
+        __syncthreads();
+        if (j < r) {
+            double w = 0.0;
+            for (int q = 0; q < S; ++q) w += part[q][j];
+            w *= beta[cc];
+#pragma unroll
+            for (int ii = 0; ii < KH; ++ii) qc[ii] -= w * sv[row0 + ii];
+        }
+    }
+    if (j < r) {
+#pragma unroll
+        for (int ii = 0; ii < KH; ++ii)
+            if (row0 + ii < k) d.X[(row0 + ii) + (int64_t)j * d.ldx] = qc[ii];
+    }
+    if (tid == 0) {
+        d.rank[0] = r;
+        d.rank[1] = rr;
+        *d.flag = insufficient;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_qrcp_reg(const SmallDesc *__restrict__ descs, double tol, int min_tail,
+                                                    int k_full, int rank_cap, DevParams *params) {
+    const SmallDesc d = descs[blockIdx.x];
+    const int k = d.k_dev ? *d.k_dev : d.k;
+    if (k <= kJacK || k > kRegK) return;  // handled by k_qrcp_trunc
+    qrcp_reg<kRegK / 4, 4>(d, k, tol * tol, min_tail, k_full, rank_cap, params, d.R);
+}
+
+__global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict__ descs, double tol, int min_tail,
+                                                     int k_full, int rank_cap, DevParams *params) {
+    __shared__ double lds[kJacK * (kJacK + 1)];
+    __shared__ double cn[kMaxSketch];
+    __shared__ double beta[kMaxSketch];
+    __shared__ int perm[kMaxSketch];
+    __shared__ double red[32];
+    __shared__ int ired[8];
+    __shared__ int s_r;
+    const SmallDesc d = descs[blockIdx.x];
+    const int k = d.k_dev ? *d.k_dev : d.k;
+    const int tid = threadIdx.x;
+    if (k <= 0 || k > kMaxSketch) {
+        if (tid == 0) {
+            d.rank[0] = d.rank[1] = 0;
+            *d.flag = 0;
+            if (k > kMaxSketch) set_status(params, TLR_RANK_OVERFLOW, d.tile_i, d.tile_j);
+        }
+        return;
+    }
+    if (k > kJacK && k <= kRegK) return;  // k_qrcp_reg
+    double *M = (k <= kJacK) ? lds : d.R;  // row-major working copy
+    const int ldm = (k <= kJacK) ? k + 1 : k;
+    for (int e = tid; e < k * k; e += 256) {
+        const int i = e / k, j = e - (e / k) * k;
+        M[i * ldm + j] = d.A[i + (int64_t)j * d.lda];
+    }
+    __syncthreads();
+    qrcp_trunc<256>(M, ldm, k, tol * tol, cn, beta, perm, red, ired, &s_r);
+    // a rank within min_tail of the sample width means the sample was too
+    // narrow: keep the previous factors (rank 0 written) and let the host retry
+    const int insufficient = (k - s_r < min_tail) && (k < (d.k_full < k_full ? d.k_full : k_full));
+    int r = insufficient ? 0 : s_r;
+    if (!insufficient && r > rank_cap) {
+        if (tid == 0) set_status(params, TLR_RANK_OVERFLOW, d.tile_i, d.tile_j);
+        r = rank_cap;
+    }
+    // Y = B^T (k x r): B[c][perm[j]] = R[c][j] for j >= c (R[c][c] = alpha_c, kept in cn[c])
+    for (int e = tid; e < k * r; e += 256) {
+        const int c = e / k, j = e - c * k;  // row c of B, column j (pivoted order)
+        double v;
+        if (j < c) v = 0.0;
+        else if (j == c) v = cn[c];
+        else v = M[c * ldm + j];
+        d.Y[perm[j] + (int64_t)c * d.ldy] = v;
+    }
+    // X = Q1 = H_0 ... H_{r-1} [I_r; 0], backward accumulation, column q by thread
+    for (int q = tid; q < r; q += 256) {
+        double *xq = d.X + (int64_t)q * d.ldx;
+        for (int i = 0; i < k; ++i) xq[i] = (i == q) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int c = r - 1; c >= 0; --c) {
+        const double bta = beta[c];
+        for (int q = tid; q < r; q += 256) {
+            double *xq = d.X + (int64_t)q * d.ldx;
+            double w = 0.0;
+            for (int i = c; i < k; ++i) w += M[i * ldm + c] * xq[i];
+            w *= bta;
+            for (int i = c; i < k; ++i) xq[i] -= w * M[i * ldm + c];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d.rank[0] = r;
+        d.rank[1] = s_r;
+        *d.flag = insufficient;
+    }
+}
+
 // ------------------------------------------------- dense diagonal tiles --
 
 // Cholesky of one bs x bs diagonal block A[b0:b0+bs, b0:b0+bs] (ld) in LDS.
@@ -455,17 +964,36 @@ __global__ __launch_bounds__(64) void k_trsm_block(const double *__restrict__ L,
 }  // namespace
 
 tlr_status chol_small(const SmallDesc *d_descs, int count, int max_k, int mode, DevParams *params,
-                      hipStream_t s) {
+                      hipStream_t s, const SmallDesc *h_descs) {
     (void)max_k;
     if (count <= 0) return TLR_OK;
+    static const int cls = ktimer_class("k_chol_small");
+    double flops = 0.0, bytes = 0.0;
+    if (h_descs && ktimer_on())
+        for (int t = 0; t < count; ++t) {
+            const double k = h_descs[t].k;
+            flops += k * k * k / 3.0;
+            bytes += 8.0 * k * (k + 1.0);  // lower triangle in, upper factor out
+        }
+    KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
     hipLaunchKernelGGL(k_chol_small, dim3(count), dim3(kSmallThreads), 0, s, d_descs, mode, params);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }
 
-tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, hipStream_t s) {
+tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, hipStream_t s,
+                     const SmallDesc *h_descs) {
     (void)max_k;
     if (count <= 0 || max_m <= 0) return TLR_OK;
+    static const int cls = ktimer_class("k_trsm_rows");
+    double flops = 0.0, bytes = 0.0;
+    if (h_descs && ktimer_on())
+        for (int t = 0; t < count; ++t) {
+            const double k = h_descs[t].k, m = h_descs[t].m;
+            flops += m * k * k;
+            bytes += 8.0 * (2.0 * m * k + k * (k + 1.0) / 2.0);
+        }
+    KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
     hipLaunchKernelGGL(k_trsm_rows, dim3((unsigned)cdiv(max_m, 64), count), dim3(64), 0, s, d_descs);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
@@ -475,8 +1003,29 @@ tlr_status jacobi_svd(const SmallDesc *d_descs, int count, int max_k, double tol
                       int k_full, int rank_cap, DevParams *params, hipStream_t s) {
     (void)max_k;
     if (count <= 0) return TLR_OK;
+    static const int cls = ktimer_class("k_jacobi_svd");
+    KTimer kt(cls, s, 0.0, 0.0, false);  // iterative: no fixed operation count
     hipLaunchKernelGGL(k_jacobi_svd, dim3(count), dim3(kSmallThreads), 0, s, d_descs, tol, min_tail,
                        k_full, rank_cap, params);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status qrcp_trunc(const SmallDesc *d_descs, int count, int max_k, double tol, int min_tail, int k_full,
+                      int rank_cap, DevParams *params, hipStream_t s) {
+    if (count <= 0) return TLR_OK;
+    static const int cls_t = ktimer_class("k_qrcp_trunc"), cls_r = ktimer_class("k_qrcp_reg");
+    {
+        // the stopping step (the rank) is decided on the device
+        KTimer kt(cls_t, s, 0.0, 0.0, false);
+        hipLaunchKernelGGL(k_qrcp_trunc, dim3(count), dim3(256), 0, s, d_descs, tol, min_tail, k_full, rank_cap,
+                           params);
+    }
+    if (max_k > kJacK) {
+        KTimer kt(cls_r, s, 0.0, 0.0, false);
+        hipLaunchKernelGGL(k_qrcp_reg, dim3(count), dim3(1024), 0, s, d_descs, tol, min_tail, k_full, rank_cap,
+                           params);
+    }
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }

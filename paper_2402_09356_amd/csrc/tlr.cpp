@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "ktimer.h"
 
 struct tlr_plan_s {
     int64_t n, npad, ntiles;
@@ -28,7 +29,7 @@ struct tlr_plan_s {
     tlr_precision prec;
     uint32_t flags;
     size_t off_params, off_x, off_y, off_diag, off_rsig, off_rL, off_tstat, off_slots, off_yvec, off_omega,
-        off_desc, off_arena;
+        off_desc, off_arena, off_knu;
     size_t desc_bytes, arena_bytes, ws_bytes;
 };
 
@@ -108,6 +109,7 @@ struct Ctx {
     }
     tlr_status sync_reset() {
         TLR_HIP(hipStreamSynchronize(s));
+        ktimer_poll();
         desc_used = 0;
         return TLR_OK;
     }
@@ -155,7 +157,7 @@ tlr_status launch_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v
         const size_t cnt = std::min<size_t>(65535, v.size() - off);
         auto *d = c.push(v.data() + off, cnt);
         if (!d) return TLR_E_NOMEM;
-        TLR_TRY(gemm_batched(ta, tb, d, (int)cnt, mm, mn, c.s));
+        TLR_TRY(gemm_batched(ta, tb, d, (int)cnt, mm, mn, c.s, v.data() + off));
     }
     return TLR_OK;
 }
@@ -241,11 +243,14 @@ tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega,
 // and each shifted pass lifts the directions it cannot resolve yet -- then two
 // plain passes with deflation of null directions, which restore
 // orthonormality to rounding level.  Optionally R = R4 R3 R2 R1 (panel = Q R).
-tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r) {
+// With passes = 2 or 3 the result spans the panel's range with every
+// direction above the rounding level lifted to unit size, which is all the
+// first basis of the range finder needs.
+tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int passes = 4) {
     const int nb = c.p->nb;
     int kmx = 0;
     for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
-    for (int it = 0; it < 4; ++it) {
+    for (int it = 0; it < passes; ++it) {
         std::vector<GemmDesc> gram;
         std::vector<SmallDesc> sd;
         for (auto &jb : jobs) {
@@ -266,8 +271,8 @@ tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r) {
         }
         TLR_TRY(launch_gemms(c, true, false, gram));
         TLR_PUSH(dsd, c, sd);
-        TLR_TRY(chol_small(dsd, (int)sd.size(), kmx, it < 2 ? 1 : 2, c.params(), c.s));
-        TLR_TRY(trsm_rows(dsd, (int)sd.size(), nb, kmx, c.s));
+        TLR_TRY(chol_small(dsd, (int)sd.size(), kmx, it < 2 ? 1 : 2, c.params(), c.s, sd.data()));
+        TLR_TRY(trsm_rows(dsd, (int)sd.size(), nb, kmx, c.s, sd.data()));
     }
     if (want_r) {
         // Rt = R4 R3 R2 R1, accumulated through T
@@ -286,19 +291,67 @@ tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r) {
 }
 
 // Range finder with one power step:  Y = T W  (W = Gaussian), Q1 = orth(Y);
-// Z = T^T Q1, Q2 = orth(Z);  W = T Q2 = Qw Rt;  Rt = X S Yr^T (Jacobi);
-// T ~ Qw X_r S_r Yr_r^T Q2^T  =>  U = Qw X_r,  V = Q2 (Rt^T X_r).
-tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, int Rj) {
+// Z = T^T Q1, Q2 = orth(Z);  W = T Q2 = Qw Rt, so T ~ Qw Rt Q2^T.  Truncation
+// of Rt at tol:
+//  * exact_svd: Rt = X S Yr^T (one-sided Jacobi), rank = #{S > tol},
+//    U = Qw X_r, V = Q2 (Rt^T X_r)  -- the singular-value rank of the paper;
+//  * otherwise: pivoted QR of Rt stopped when the trailing block has
+//    Frobenius norm <= tol, Rt ~ Q1 B, U = Qw Q1, V = Q2 B^T (error <= tol,
+//    rank at most a few above the singular-value rank, far cheaper).
+// Q1 takes two shifted passes while tol >= 1e-12 nb sigma2 (nb sigma2 bounds
+// every tile's 2-norm): below about 1e-13 ||T|| two passes leave Q1 too
+// ill-conditioned to carry the smallest wanted directions into T^T Q1, and a
+// third (deflating) pass restores them.
+int q1_passes(const tlr_plan_s *p, double sigma2, double tol) {
+    return tol >= 1e-12 * (double)p->nb * sigma2 ? 2 : 3;
+}
+
+tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, int Rj, bool exact_svd,
+                int passes_q1) {
     if (jobs.empty()) return TLR_OK;
     const int nb = c.p->nb;
     int kmx = 0;
     for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
     TLR_TRY(apply_op(c, jobs, false, true, false, Yj, Rj));   // Yb = T W
-    TLR_TRY(cholqr(c, jobs, false, false));                  // Yb = Q1
+    TLR_TRY(cholqr(c, jobs, false, false, passes_q1));       // Yb = Q1 (only its span is used)
     TLR_TRY(apply_op(c, jobs, true, false, true, Yj, Rj));    // Zb = T^T Q1
     TLR_TRY(cholqr(c, jobs, true, false));                   // Zb = Q2
     TLR_TRY(apply_op(c, jobs, false, false, false, Yj, Rj));  // Yb = T Q2
     TLR_TRY(cholqr(c, jobs, false, true));                   // Yb = Qw, Rt
+    if (!exact_svd) {
+        std::vector<SmallDesc> sq;
+        for (auto &jb : jobs) {
+            SmallDesc d{};
+            d.A = jb.Rt;
+            d.lda = jb.k;
+            d.R = jb.G;  // scratch
+            d.ldr = jb.k;
+            d.X = jb.Xs;
+            d.ldx = jb.k;
+            d.Y = jb.P;
+            d.ldy = jb.k;
+            d.rank = jb.stat;
+            d.flag = jb.stat + 2;
+            d.k = jb.k;
+            d.k_full = jb.kfull;
+            d.tile_i = jb.i;
+            d.tile_j = jb.j;
+            sq.push_back(d);
+        }
+        TLR_PUSH(dsq, c, sq);
+        TLR_TRY(qrcp_trunc(dsq, (int)sq.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s));
+        std::vector<GemmDesc> gu2, gv2;
+        for (auto &jb : jobs) {
+            GemmDesc a = gd(jb.Yb, nb, jb.Xs, jb.k, jb.Uout, nb, nb, 0, jb.k, 1.0, 0.0);
+            a.N_dev = jb.stat;
+            gu2.push_back(a);
+            GemmDesc v = gd(jb.Zb, nb, jb.P, jb.k, jb.Vout, nb, nb, 0, jb.k, 1.0, 0.0);
+            v.N_dev = jb.stat;
+            gv2.push_back(v);
+        }
+        TLR_TRY(launch_gemms(c, false, false, gu2));
+        return launch_gemms(c, false, false, gv2);
+    }
     std::vector<SmallDesc> sd;
     for (auto &jb : jobs) {
         SmallDesc d{};
@@ -349,6 +402,31 @@ int clamp_k(const tlr_plan_s *p, int want, int kfull) {
     return std::max(1, std::min(k, cap));
 }
 
+// Smallest ladder width >= want (see widen_k).
+int ladder_k(const tlr_plan_s *p, int want, int kfull) {
+    static const int ladder[] = {32, 64, 112, 176, 240, 320, 400, 512};
+    int k = want;
+    for (int w : ladder)
+        if (w >= want) {
+            k = w;
+            break;
+        }
+    return clamp_k(p, k, kfull);
+}
+
+// Next sketch width after a too-narrow sample: a fixed ladder that stays at
+// the widths the small kernels handle in LDS as long as possible.
+int widen_k(const tlr_plan_s *p, int k, int kfull) {
+    static const int ladder[] = {32, 64, 112, 176, 240, 320, 400, 512};
+    int next = 2 * k;
+    for (int w : ladder)
+        if (w > k) {
+            next = w;
+            break;
+        }
+    return std::max(clamp_k(p, next, kfull), std::min(k, std::min(p->kmax, kfull)));
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ plan --
@@ -390,6 +468,7 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->off_slots = take(sizeof(double) * 2 * (size_t)nb * rcap * (size_t)p->ntiles);
     p->off_yvec = take(sizeof(double) * p->npad);
     p->off_omega = take(sizeof(double) * (size_t)nb * p->kmax);
+    p->off_knu = take(sizeof(double) * kChebPieces * (kChebDeg + 1));
     p->desc_bytes = 8u << 20;
     p->off_desc = take(p->desc_bytes);
     // arena: one full wave of dense-tile jobs, plus the factorisation's
@@ -418,6 +497,7 @@ tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws,
     MaternConst mc{};
     if (!make_matern_const(th.sigma2, th.beta, th.nu, &mc)) return TLR_E_INVAL;
     Ctx c(p, d_ws, s);
+    TLR_TRY(build_knu_table(&mc, reinterpret_cast<double *>(c.ws + p->off_knu), s));
     ParamsBlock hb{};
     TLR_HIP(hipMemcpyAsync(&hb, c.pblock(), sizeof(ParamsBlock), hipMemcpyDeviceToHost, s));
     TLR_HIP(hipStreamSynchronize(s));
@@ -503,7 +583,7 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
             }
             TLR_PUSH(dg, c, gens);
             TLR_TRY(gen_tiles_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), mc, s));
-            TLR_TRY(rsvd(c, jobs, tol, nullptr, 0));
+            TLR_TRY(rsvd(c, jobs, tol, nullptr, 0, d_ranks != nullptr, q1_passes(p, hb.dp.sigma2, tol)));
             std::vector<int32_t> st(4 * jobs.size());
             // gather the per-tile status words
             for (size_t q = 0; q < jobs.size(); ++q)
@@ -519,8 +599,7 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
             for (size_t q = 0; q < jobs.size(); ++q) {
                 const Job &jb = jobs[q];
                 if (st[4 * q + 2]) {
-                    const int wider = clamp_k(p, 2 * jb.k, jb.kfull);
-                    retry.push_back({jb.i, jb.j, std::max(wider, jb.k)});
+                    retry.push_back({jb.i, jb.j, widen_k(p, jb.k, jb.kfull)});
                 } else {
                     const int num = st[4 * q + 1];
                     ranks[(size_t)jb.i * nt + jb.j] = (num > p->rcap) ? -1 : st[4 * q];
@@ -616,7 +695,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             std::vector<int> kk(nt, 0);
             for (int i : todo) {
                 const int kfull = std::min(tile_rows(p, i), tile_rows(p, j));
-                kk[i] = clamp_k(p, r[(size_t)i * nt + j] + p->pover, kfull);
+                kk[i] = ladder_k(p, r[(size_t)i * nt + j] + p->pover, kfull);
             }
             while (!todo.empty()) {
                 std::vector<int> retry;
@@ -670,7 +749,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                     }
                     TLR_TRY(launch_gemms(c, true, false, gmm));
                     TLR_TRY(launch_gemms(c, false, false, gxx));
-                    TLR_TRY(rsvd(c, jobs, tol, Yj, Rj));
+                    TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, false, q1_passes(p, hb.dp.sigma2, tol)));
                     std::vector<int32_t> st(4 * jobs.size());
                     for (size_t q = 0; q < jobs.size(); ++q)
                         TLR_HIP(hipMemcpyAsync(&st[4 * q], jobs[q].stat, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -684,7 +763,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                     for (size_t q = 0; q < jobs.size(); ++q) {
                         const Job &jb = jobs[q];
                         if (st[4 * q + 2]) {
-                            kk[jb.i] = std::max(clamp_k(p, 2 * jb.k, jb.kfull), jb.k);
+                            kk[jb.i] = widen_k(p, jb.k, jb.kfull);
                             retry.push_back(jb.i);
                         } else {
                             r[(size_t)jb.i * nt + j] = st[4 * q];

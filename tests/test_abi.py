@@ -79,3 +79,15 @@ def test_diag_entry_checks():
     fake = ctypes.c_void_p(0x1000)
     assert L.tlr_diag_gemm(0, 0, 4, 4, 4, 1.0, fake, 2, fake, 4, 0.0, fake, 4, None) == 1
     assert L.tlr_diag_svd(1, 600, fake, 1e-9, fake, fake, fake, fake, None) == 1
+
+
+def test_launch_timer_host_side():
+    """The timer's host bookkeeping works without a device: enabling,
+    resetting and reading with nothing pending, and argument checks."""
+    L = B.lib()
+    assert L.tlr_kstats_read(None, 4) == -1
+    B.kstats_enable(True)
+    B.kstats_reset()
+    stats = B.kstats()
+    assert all(s["launches"] == 0 and s["total_ms"] == 0.0 for s in stats)
+    B.kstats_enable(False)

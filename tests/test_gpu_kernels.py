@@ -1,6 +1,7 @@
 """Building blocks through the C ABI: the float64 matrix-core GEMM and the
 one-sided Jacobi SVD, against NumPy."""
 import numpy as np
+import scipy.linalg
 import pytest
 import torch
 
@@ -68,3 +69,55 @@ def test_jacobi_svd_graded_spectrum(k):
         assert np.max(np.abs(G - np.eye(r))) < 1e-10
         proj = Xt[:, :r].T @ mats[t]
         np.testing.assert_allclose(np.linalg.norm(proj, axis=1), S[t][:r], rtol=0, atol=1e-13 * ref[0])
+
+
+@pytest.mark.parametrize("k", [16, 64, 112, 124, 125, 150, 176, 200])
+def test_cholqr_rank_deficient_panel(k):
+    """The four-pass CholeskyQR: Q orthonormal on its live columns, Y = Q R,
+    singular values of R equal those of Y down to rounding."""
+    device()
+    m = 900
+    rng = np.random.default_rng(k)
+    r = max(1, k // 2)
+    Y = rng.standard_normal((m, r)) @ (rng.standard_normal((r, k)) * np.logspace(0, -11, r)[:, None])
+    Y += 1e-17 * rng.standard_normal((m, k))
+    Qt, Rt = B.diag_cholqr(colmajor(Y))
+    torch.cuda.synchronize()
+    Q, R = from_colmajor(Qt), from_colmajor(Rt)
+    np.testing.assert_allclose(Q @ R, Y, rtol=0, atol=1e-14 * np.linalg.norm(Y, 2))
+    live = np.linalg.norm(Q, axis=0) > 0.5
+    G = Q[:, live].T @ Q[:, live]
+    assert np.max(np.abs(G - np.eye(live.sum()))) < 1e-13
+    sy = np.linalg.svd(Y, compute_uv=False)
+    sr = np.linalg.svd(R, compute_uv=False)
+    np.testing.assert_allclose(sr, sy, rtol=0, atol=1e-13 * sy[0])
+
+
+@pytest.mark.parametrize("k", [16, 64, 112, 113, 150, 176, 200])
+def test_qrcp_truncation(k):
+    """Truncated pivoted QR: ||A - Q1 B||_2 <= tol, Q1 orthonormal, rank at
+    least the singular-value rank and equal (up to a pivot tie) to the first
+    step at which LAPACK's pivoted QR has trailing Frobenius norm <= tol."""
+    device()
+    rng = np.random.default_rng(100 + k)
+    mats = []
+    for t in range(3):
+        u, _ = np.linalg.qr(rng.standard_normal((k, k)))
+        v, _ = np.linalg.qr(rng.standard_normal((k, k)))
+        s = 10.0 * np.exp(-np.arange(k) * (25.0 / k))
+        mats.append((u * s) @ v.T)
+    tol = 1e-7
+    X, Bt, rank = B.diag_qrcp(torch.stack([colmajor(a) for a in mats]), tol)
+    torch.cuda.synchronize()
+    X, Bt, rank = X.cpu().numpy(), Bt.cpu().numpy(), rank.cpu().numpy()
+    for t in range(3):
+        r = int(rank[t])
+        Q1 = X[t].T[:, :r]
+        Bm = Bt[t].T[:, :r].T
+        err = np.linalg.norm(mats[t] - Q1 @ Bm, 2)
+        assert err <= tol * 1.0001, (k, t, r, err)
+        assert np.max(np.abs(Q1.T @ Q1 - np.eye(r))) < 1e-13
+        svr = int(np.count_nonzero(np.linalg.svd(mats[t], compute_uv=False) > tol))
+        Rl = scipy.linalg.qr(mats[t], pivoting=True, mode="r")[0]
+        rl = next(c for c in range(k + 1) if np.linalg.norm(Rl[c:, c:]) <= tol)
+        assert svr <= r and abs(r - rl) <= 1, (r, rl, svr)

@@ -202,3 +202,29 @@ def test_collinear_ar1_exact_at_scale():
     # off-diagonal tiles of the exponential kernel on a sorted line have rank 1
     low = ranks[np.tril_indices(plan.nt, -1)]
     assert np.all(low <= 1)
+
+
+@pytest.mark.parametrize("kind,tol,maxrank", [("morton", 1e-9, 0), ("hilbert", 1e-7, 0), ("kdtree", 1e-9, 0),
+                                              ("morton", 1e-12, 200)])
+def test_fast_truncation_path(kind, tol, maxrank):
+    """Without a rank request the compression truncates by pivoted QR
+    (trailing Frobenius norm <= tol): error per tile <= tol, l within bound.
+    At tol = 1e-12 the ranks reach ~125, so the sketch widths exercise the
+    wide (packed / register-resident) small kernels."""
+    device()
+    theta, nb = (1.0, 0.1, 0.5), 200
+    locs, z = make_problem(40, theta, kind)
+    plan = B.Plan(1600, nb, maxrank=maxrank)
+    ws = plan.workspace()
+    out = plan.loglik(ws, to_dev(locs), to_dev(z), theta, tol).cpu().numpy()
+    dense = OL.loglik_dense(locs, z, theta).loglik
+    comp, oranks = OT.compressed_loglik(locs, z, theta, nb, tol, maxrank=maxrank or None)
+    assert abs(out[2] - dense) <= bound(1600, tol, comp.loglik - dense)
+    plan.gen_tiles(ws, to_dev(locs), theta)
+    plan.compress(ws, tol)
+    sig = OM.covariance_matrix(locs, theta)
+    for (i, j) in [(1, 0), (4, 3), (7, 2)]:
+        tile, r = plan.tile(ws, i, j)
+        ref = sig[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
+        assert np.linalg.norm(tile - ref, 2) <= 1.5 * tol + 1e-15 * np.linalg.norm(ref, 2)
+        assert oranks[i, j] <= r <= oranks[i, j] + 12
