@@ -49,6 +49,53 @@ def cpu_baseline(locs_ordered: np.ndarray, z_ordered: np.ndarray, theta, n_full:
                       f"ordered points: {dt:.2f} s; evals/s scaled to n={n_full} by (n/{sample_n})^3"}
 
 
+# MI355X published peaks used for roofline fractions
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6      # FP64 matrix (MFMA) and FP64 vector alike
+VALU_KERNELS = ("k_chol_small", "k_trsm_rows", "k_trsv_tile", "k_qrcp_trunc", "k_qrcp_reg", "k_jacobi_svd",
+                "k_lr_gemv", "k_gen_tiles")
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factor), if it was
+    taken for these kernel sources and this workload; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    from paper_2402_09356_amd.traffic import source_digest
+
+    if rec.get("source_sha256") != source_digest() or rec.get("workload") != workload:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
+def roofline(stats, workload: str):
+    """Roofline record of the kernel with the largest total launch time."""
+    top = stats[0]
+    if top["exact_launches"] == 0 or top["exact_ms"] <= 0.0:
+        return {"kernel": top["name"], "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "avg_launch_us": 1e3 * top["total_ms"] / max(top["launches"], 1),
+                "launches": top["launches"], "note": "work of this kernel is decided on the device"}
+    sec = top["exact_ms"] * 1e-3
+    t_flops = top["flops"] / (PEAK_FP64_TFLOPS * 1e12)
+    t_bytes = top["bytes"] / (PEAK_HBM_GBS * 1e9)
+    per = top["exact_launches"]
+    if t_bytes >= t_flops:
+        bound, achieved, peak, unit = "hbm", top["bytes"] / sec / 1e9, PEAK_HBM_GBS, "GB/s"
+    else:
+        bound = "alu" if top["name"] in VALU_KERNELS else "mfma"
+        achieved, peak, unit = top["flops"] / sec / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
+    return {"kernel": top["name"], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": measured_traffic(top["name"], workload),
+            "avg_launch_us": 1e3 * top["total_ms"] / max(top["launches"], 1), "launches": top["launches"],
+            "algorithmic_bytes_per_launch": top["bytes"] / per, "algorithmic_flops_per_launch": top["flops"] / per,
+            "share_of_kernel_time": top["total_ms"] / sum(s["total_ms"] for s in stats)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +105,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=10000)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size before warmup (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this build", file=sys.stderr)
@@ -88,12 +137,20 @@ def main():
     torch.cuda.synchronize()
     print(f"# workspace {plan.ws_bytes / 2**30:.2f} GiB, nt={plan.nt}, maxrank={plan.maxrank}", file=sys.stderr,
           flush=True)
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for w in range(args.warmup):
         plan.loglik(ws, olocs, oz, thetas[w], tol, out=out)
         torch.cuda.synchronize()
         print(f"# warmup {w}: l={out[2].item():.6f}", file=sys.stderr, flush=True)
     lat = []
     lls = []
+    B.kstats_enable(True)
+    B.kstats_reset()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
@@ -105,8 +162,15 @@ def main():
         print(f"# step {k}: {lat[-1] * 1e3:.1f} ms l={lls[-1]:.6f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    stats = B.kstats()
+    B.kstats_enable(False)
+    for k in stats[:12]:
+        print(f"# {k['name']:20s} launches {k['launches']:7d}  total {k['total_ms']:10.2f} ms  "
+              f"avg {1e3 * k['total_ms'] / max(k['launches'], 1):9.2f} us", file=sys.stderr)
     st = plan.status(ws)
     lat_ms = np.asarray(lat) * 1e3
+    workload = (f"{args.config}: n={n} jittered grid, nu=0.5 beta=0.1 sigma2=1, {kind} order, nb={nb}, "
+                f"tol={tol:g}, theta=theta_true*exp(0.2 N(0,I)) per step")
     rec = {
         "metric": "l(theta) evals/s, n=90k TLR Matern",
         "value": args.steps / total,
@@ -120,14 +184,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: n={n} jittered grid, nu=0.5 beta=0.1 sigma2=1, {kind} order, "
-                               f"nb={nb}, tol={tol:g}, theta=theta_true*exp(0.2 N(0,I)) per step",
+        "config": {"workload": workload,
                    "n": n, "nb": nb, "tol": tol, "ordering": kind, "precision": args.precision},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "max_rank": st["max_rank"],
         "rank_sum": st["rank_sum"],
         "all_finite": bool(np.all(np.isfinite(lls))),
-        "roofline": None,
+        "roofline": roofline(stats, workload),
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -264,7 +264,7 @@ extern "C" tlr_status tlr_diag_cholqr(int32_t m, int32_t k, double *d_Y, double 
         g.alpha = 1.0; g.beta = 0.0;
         hg[it] = g;
         tlr::SmallDesc d{};
-        d.A = G; d.lda = k; d.R = Rp[it]; d.ldr = k; d.Y = d_Y; d.ldy = m; d.m = m; d.k = k;
+        d.A = G; d.lda = k; d.R = Rp[it]; d.ldr = k; d.X = T2; d.Y = d_Y; d.ldy = m; d.m = m; d.k = k;
         hsd[it] = d;
     }
     auto mul = [&](const double *A, const double *B, double *C) {

@@ -1,0 +1,348 @@
+// The two halves of one CholeskyQR pass on the matrix cores:
+//  * k_chol_small: Cholesky of a k x k Gram matrix (shifted CholeskyQR,
+//    Fukaya, Kannan, Nakatsukasa, Zhang, Yamamoto, SIAM J. Sci. Comput. 2020;
+//    deflation of null directions), right-looking over 16 x 16 tiles;
+//  * k_trsm_rows: Y <- Y R^-1 for the m x k panel, 16 columns at a time.
+//
+// Tiles.  The lower triangle is held as 16 x 16 tiles, tile (i, j), i >= j,
+// at index i(i+1)/2 + j, each stored column-major with a column pitch of 17
+// words (the pitch keeps both MFMA operand reads and accumulator writes free
+// of bank conflicts).  Up to 11 tile rows (k <= 176) live in LDS, sized per
+// launch; beyond that the tiles live in the job's k x k scratch (d.X), which
+// stays in L2.  k is padded to a multiple of 16 with an identity block.
+//
+// One step b of the factorisation:
+//   1. one wave factors the diagonal tile in registers (lane r holds row r,
+//      columns meet through cross-lane shuffles);
+//   2. every row of the panel below is solved against it (one thread a row);
+//   3. every trailing tile (i, j), b < j <= i, takes A_ij -= L_ib L_jb^T with
+//      four v_mfma_f64_16x16x4 (one wave a tile).
+// Pivot rule (same as the unblocked algorithm in exact arithmetic): a pivot
+// that is not finite fails; with defl == 0 a pivot <= 0 fails; with defl > 0
+// a pivot <= defl is a dead direction whose whole column of L is zero, so the
+// row solve writes a zero column of Q there.
+#include <cmath>
+
+#include "kernels.h"
+#include "ktimer.h"
+
+namespace tlr {
+namespace {
+
+constexpr int kT = 16;
+constexpr int kTP = 17;
+constexpr int kTW = kT * kTP;
+constexpr int kCholLdsTiles = 11;
+constexpr int kThreads = 256;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __host__ inline int tri(int i) { return i * (i + 1) / 2; }
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Factor the tiles in TS (tile rows T); returns the failing column + 1, or 0.
+template <bool LDS>
+__device__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, int *s_fail) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int b = 0; b < T; ++b) {
+        // 1. diagonal tile
+        if (wave == 0) {
+            double *D = TS + (tri(b) + b) * kTW;
+            const int r = lane & 15;
+            double a[kT];
+#pragma unroll
+            for (int q = 0; q < kT; ++q) a[q] = D[r + kTP * q];
+            int fail = 0;
+#pragma unroll
+            for (int c = 0; c < kT; ++c) {
+                const double piv = __shfl(a[c], c, 64);
+                const int gc = kT * b + c;
+                double lcc, iv;
+                if (gc >= k) {  // padding
+                    lcc = 1.0;
+                    iv = 1.0;
+                } else if (!isfinite(piv) || (defl == 0.0 && !(piv > 0.0))) {
+                    if (!fail) fail = gc + 1;
+                    lcc = 0.0;
+                    iv = 0.0;
+                } else if (defl > 0.0 && piv <= defl) {
+                    lcc = 0.0;  // dead direction
+                    iv = 0.0;
+                } else {
+                    lcc = sqrt(piv);
+                    iv = 1.0 / lcc;
+                }
+                const double lrc = (r == c) ? lcc : ((r > c) ? a[c] * iv : 0.0);
+                a[c] = lrc;
+#pragma unroll
+                for (int q = c + 1; q < kT; ++q) a[q] -= lrc * __shfl(lrc, q, 64);
+                if (lane == c) inv[c] = iv;
+            }
+            if (lane < kT) {
+#pragma unroll
+                for (int q = 0; q < kT; ++q) D[r + kTP * q] = (q <= r) ? a[q] : 0.0;
+            }
+            if (lane == 0 && fail) *s_fail = fail;
+        }
+        __syncthreads();
+        if (*s_fail) return *s_fail;
+        const int n = T - b - 1;
+        if (n == 0) break;
+        // 2. panel rows: x L_bb^T = a
+        const double *D = TS + (tri(b) + b) * kTW;
+        for (int rr = tid; rr < kT * n; rr += kThreads) {
+            const int ti = b + 1 + (rr >> 4), r = rr & 15;
+            double *P = TS + (tri(ti) + b) * kTW;
+            double a[kT];
+#pragma unroll
+            for (int q = 0; q < kT; ++q) a[q] = P[r + kTP * q];
+#pragma unroll
+            for (int c = 0; c < kT; ++c) {
+                double s = a[c];
+#pragma unroll
+                for (int q = 0; q < c; ++q) s -= a[q] * D[c + kTP * q];
+                a[c] = s * inv[c];
+            }
+#pragma unroll
+            for (int q = 0; q < kT; ++q) P[r + kTP * q] = a[q];
+        }
+        __syncthreads();
+        // 3. trailing tiles
+        const int count = tri(n);
+        const int li = lane & 15, lg = lane >> 4;
+        for (int t = wave; t < count; t += kThreads / 64) {
+            int ip = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+            while (tri(ip + 1) <= t) ++ip;
+            while (tri(ip) > t) --ip;
+            const int i = b + 1 + ip, j = b + 1 + (t - tri(ip));
+            double *C = TS + (tri(i) + j) * kTW;
+            const double *Li = TS + (tri(i) + b) * kTW;
+            const double *Lj = TS + (tri(j) + b) * kTW;
+            v4d acc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = C[(lg + 4 * q) + kTP * li];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double av = -Li[li + kTP * (4 * s + lg)];
+                const double bv = Lj[li + kTP * (4 * s + lg)];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) C[(lg + 4 * q) + kTP * li] = acc[q];
+        }
+        __syncthreads();
+    }
+    return 0;
+}
+
+template <bool LDS>
+__device__ void load_tiles(double *TS, int T, int k, const double *A, int64_t lda, double shift) {
+    const int tid = threadIdx.x;
+    const int r = tid & 15, c = tid >> 4;  // 256 threads: one tile per pass
+    for (int ti = 0, t = 0; ti < T; ++ti)
+        for (int tj = 0; tj <= ti; ++tj, ++t) {
+            const int gr = kT * ti + r, gc = kT * tj + c;
+            double v;
+            if (gr < k && gc < k)
+                v = (gr >= gc) ? A[gr + (int64_t)gc * lda] + ((gr == gc) ? shift : 0.0) : 0.0;
+            else
+                v = (gr == gc) ? 1.0 : 0.0;
+            TS[t * kTW + r + kTP * c] = v;
+        }
+}
+
+__device__ void store_r(const double *TS, int k, double *R, int64_t ldr) {
+    for (int e = threadIdx.x; e < k * k; e += kThreads) {
+        const int r = e % k, q = e / k;
+        double v = 0.0;
+        if (r <= q) v = TS[(tri(q >> 4) + (r >> 4)) * kTW + (q & 15) + kTP * (r & 15)];
+        R[r + (int64_t)q * ldr] = v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_chol_small(const SmallDesc *__restrict__ descs, int mode,
+                                                          DevParams *params, int lds_tiles) {
+    extern __shared__ double smem[];
+    const SmallDesc d = descs[blockIdx.x];
+    const int k = d.k_dev ? *d.k_dev : d.k;
+    if (k <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int T = (k + kT - 1) / kT;
+    double *inv = smem + tri(lds_tiles) * kTW;
+    double *red = inv + kT;
+    int *s_fail = reinterpret_cast<int *>(red + 8);
+    // mode 1: shift = 11 (m k + k (k+1)) u tr(A), and an exactly-zero panel
+    // deflates instead of failing; mode 2: pivots below 1e-12 of the largest
+    // diagonal entry deflate; mode 0: plain.
+    double shift = 0.0, defl = 0.0;
+    if (mode != 0) {
+        double v = (mode == 1) ? 0.0 : 0.0;
+        for (int c = tid; c < k; c += kThreads) {
+            const double g = d.A[c + (int64_t)c * d.lda];
+            v = (mode == 1) ? v + g : fmax(v, g);
+        }
+        v = (mode == 1) ? wave_sum(v) : wave_max(v);
+        if (lane == 0) red[wave] = v;
+    }
+    if (tid == 0) *s_fail = 0;
+    __syncthreads();
+    if (mode == 1) {
+        const double tr = red[0] + red[1] + red[2] + red[3];
+        shift = 11.0 * ((double)d.m * k + (double)k * (k + 1)) * 1.1102230246251565e-16 * tr;
+        defl = 1e-300;
+    } else if (mode == 2) {
+        const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        defl = (mx > 0.0) ? 1e-12 * mx : 1e-300;
+    }
+    int fail;
+    if (T <= lds_tiles) {
+        load_tiles<true>(smem, T, k, d.A, d.lda, shift);
+        __syncthreads();
+        fail = chol_tiles<true>(smem, T, k, defl, inv, s_fail);
+        if (!fail) store_r(smem, k, d.R, d.ldr);
+    } else {
+        load_tiles<false>(d.X, T, k, d.A, d.lda, shift);
+        __syncthreads();
+        fail = chol_tiles<false>(d.X, T, k, defl, inv, s_fail);
+        if (!fail) store_r(d.X, k, d.R, d.ldr);
+    }
+    if (fail) {
+        if (tid == 0) set_status(params, TLR_NOT_SPD, -100 - d.tile_i, -100 - d.tile_j);
+        // an identity factor keeps downstream arithmetic finite
+        for (int e = tid; e < k * k; e += kThreads) {
+            const int r = e % k, q = e / k;
+            d.R[r + (int64_t)q * d.ldr] = (r == q) ? 1.0 : 0.0;
+        }
+    }
+}
+
+// Y (m x k, ldy) <- Y R^-1, R upper triangular (k x k, ldr).  A work-group of
+// four waves owns 64 rows, a wave 16 of them.  Column block b: the R block
+// R[0 : 16b+16, 16b : 16b+16] is staged in LDS; each wave takes its 16 x 16
+// block of Y, subtracts X[:, :16b] R[:16b, block] with MFMA (X read back from
+// Y, where the earlier blocks were written), and solves against the diagonal
+// block column by column across the lanes.  A zero diagonal of R (dead
+// direction) gives a zero column.
+__global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restrict__ descs) {
+    extern __shared__ double Rb[];
+    const SmallDesc d = descs[blockIdx.y];
+    const int k = d.k_dev ? *d.k_dev : d.k;
+    const int m = d.m;
+    const int r0 = blockIdx.x * 64;
+    if (k <= 0 || r0 >= m) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int rowbase = r0 + kT * wave;
+    const int T = (k + kT - 1) / kT;
+    double *__restrict__ Y = d.Y;
+    const double *__restrict__ R = d.R;
+    const int64_t ldy = d.ldy, ldr = d.ldr;
+    for (int b = 0; b < T; ++b) {
+        __syncthreads();
+        const int rows = kT * b + kT;
+        for (int e = tid; e < rows * kT; e += kThreads) {
+            const int q = e >> 4, j = e & 15, gc = kT * b + j;
+            Rb[q * kTP + j] = (q < k && gc < k) ? R[q + (int64_t)gc * ldr] : ((q == gc) ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        const int col = kT * b + li;
+        v4d acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = rowbase + lg + 4 * q;
+            acc[q] = (row < m && col < k) ? Y[row + (int64_t)col * ldy] : 0.0;
+        }
+        const int arow = rowbase + li;
+        const bool arow_ok = arow < m;
+        for (int s = 0; s < 4 * b; ++s) {
+            const int kap = 4 * s + lg;
+            const double av = arow_ok ? -Y[arow + (int64_t)kap * ldy] : 0.0;
+            const double bv = Rb[kap * kTP + li];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        const double *Rd = Rb + (kT * b) * kTP;  // rows 16b.. of the staged block
+#pragma unroll
+        for (int j = 0; j < kT; ++j) {
+            const double rjj = Rd[j * kTP + j];
+            const double iv = (rjj != 0.0) ? 1.0 / rjj : 0.0;
+            const double rjl = Rd[j * kTP + li];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double x = __shfl(acc[q] * iv, (lane & 48) + j, 64);
+                if (li == j)
+                    acc[q] = x;
+                else if (li > j)
+                    acc[q] -= x * rjl;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = rowbase + lg + 4 * q;
+            if (row < m && col < k) Y[row + (int64_t)col * ldy] = acc[q];
+        }
+    }
+}
+
+}  // namespace
+
+tlr_status chol_small(const SmallDesc *d_descs, int count, int max_k, int mode, DevParams *params,
+                      hipStream_t s, const SmallDesc *h_descs) {
+    if (count <= 0 || max_k <= 0) return TLR_OK;
+    if (max_k > kMaxSketch) return TLR_E_UNSUPPORTED;
+    static const int cls = ktimer_class("k_chol_small");
+    static const bool attr = [] {
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(k_chol_small),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+    }();
+    (void)attr;
+    double flops = 0.0, bytes = 0.0;
+    if (h_descs && ktimer_on())
+        for (int t = 0; t < count; ++t) {
+            const double k = h_descs[t].k;
+            flops += k * k * k / 3.0;
+            bytes += 8.0 * k * (k + 1.0);  // lower triangle in, upper factor out
+        }
+    const int tmax = (max_k + kT - 1) / kT;
+    const int lds_tiles = tmax < kCholLdsTiles ? tmax : kCholLdsTiles;
+    const size_t lds = sizeof(double) * ((size_t)tri(lds_tiles) * kTW + kT + 8) + 16;
+    KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
+    hipLaunchKernelGGL(k_chol_small, dim3(count), dim3(kThreads), lds, s, d_descs, mode, params, lds_tiles);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, hipStream_t s,
+                     const SmallDesc *h_descs) {
+    if (count <= 0 || max_m <= 0 || max_k <= 0) return TLR_OK;
+    if (max_k > kMaxSketch) return TLR_E_UNSUPPORTED;
+    static const int cls = ktimer_class("k_trsm_rows");
+    static const bool attr = [] {
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(k_trsm_rows),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+    }();
+    (void)attr;
+    double flops = 0.0, bytes = 0.0;
+    if (h_descs && ktimer_on())
+        for (int t = 0; t < count; ++t) {
+            const double k = h_descs[t].k, m = h_descs[t].m;
+            flops += m * k * k;
+            bytes += 8.0 * (2.0 * m * k + k * (k + 1.0) / 2.0);
+        }
+    const int kp = (max_k + kT - 1) / kT * kT;
+    const size_t lds = sizeof(double) * (size_t)kp * kTP;
+    KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
+    hipLaunchKernelGGL(k_trsm_rows, dim3((unsigned)cdiv(max_m, 64), count), dim3(kThreads), lds, s, d_descs);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+}  // namespace tlr

@@ -1,9 +1,12 @@
 // Batched float64 GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4f64).
 //
-// Each work-group computes a 64 x 64 block of one product of the batch with
-// four waves in a 2 x 2 arrangement (32 x 32 per wave = 2 x 2 MFMA tiles of
-// 16 x 16).  A and B stream through LDS in K-slices of 16, stored k-major so
-// that the 16 lanes reading one MFMA operand column touch consecutive words.
+// The products here are skinny: K is a tile edge (hundreds) while M x N is a
+// sketch or a Gram matrix (tens to a few hundred).  A work-group owns one
+// 32 x 32 block of C; its four waves split K (16-wide slices, wave w takes
+// slices w, w+4, ...) and each computes the whole block over its slices
+// (2 x 2 MFMA tiles), reading its operands straight from global memory in
+// MFMA operand layout, one slice ahead of the arithmetic.  The four partial
+// blocks meet once in LDS and are summed in a fixed order (deterministic).
 // Sizes are per product (possibly device-resident); work-groups whose block
 // lies outside their product exit at once, so the grid is sized by the
 // largest product.
@@ -13,14 +16,36 @@
 namespace tlr {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
-constexpr int PADM = BM + 4;  // LDS row pitch (doubles) to spread banks
-constexpr int PADN = BN + 4;
+constexpr int BM = 32, BN = 32, BK = 16;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+struct Slice {
+    double a[4][2], b[4][2];  // [k step][tile]
+};
+
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *__restrict__ descs, int tiles_n) {
+__device__ inline void load_slice(Slice &sl, const double *__restrict__ A, int64_t lda, const double *__restrict__ B,
+                                  int64_t ldb, int m0, int n0, int k0, int M, int N, int K, int li, int lk) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int kk = k0 + 4 * t + lk;
+        const bool kin = kk < K;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int r = m0 + 16 * i + li;
+            sl.a[t][i] = (kin && r < M) ? (TA ? A[kk + r * lda] : A[r + kk * lda]) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = n0 + 16 * j + li;
+            sl.b[t][j] = (kin && c < N) ? (TB ? B[c + kk * ldb] : B[kk + c * ldb]) : 0.0;
+        }
+    }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *descs, int tiles_n) {
     const GemmDesc d = descs[blockIdx.y];
     const int M = d.M_dev ? *d.M_dev : d.M;
     const int N = d.N_dev ? *d.N_dev : d.N;
@@ -29,13 +54,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *__restrict__ d
     const int m0 = tm * BM, n0 = tn * BN;
     if (m0 >= M || n0 >= N) return;
 
-    __shared__ double As[BK][PADM];
-    __shared__ double Bs[BK][PADN];
+    __shared__ double red[4][BM * BN];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
+    const double *__restrict__ A = d.A;
+    const double *__restrict__ B = d.B;
+    const int64_t lda = d.lda, ldb = d.ldb;
 
     v4d acc[2][2];
 #pragma unroll
@@ -43,82 +69,43 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *__restrict__ d
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    const double *__restrict__ A = d.A;
-    const double *__restrict__ B = d.B;
-    const int64_t lda = d.lda, ldb = d.ldb;
-
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        // A slice: BM x BK elements of op(A)
+    const int nsl = (K + BK - 1) / BK;
+    Slice cur, nxt;
+    if (wave < nsl) load_slice<TA, TB>(cur, A, lda, B, ldb, m0, n0, wave * BK, M, N, K, li, lk);
+    for (int s = wave; s < nsl; s += 4) {
+        if (s + 4 < nsl) load_slice<TA, TB>(nxt, A, lda, B, ldb, m0, n0, (s + 4) * BK, M, N, K, li, lk);
 #pragma unroll
-        for (int r = 0; r < (BM * BK) / 256; ++r) {
-            const int e = tid + r * 256;
-            int mm, kk;
-            if (!TA) {
-                mm = e % BM;
-                kk = e / BM;
-            } else {
-                kk = e % BK;
-                mm = e / BK;
-            }
-            const int gm = m0 + mm, gk = k0 + kk;
-            double v = 0.0;
-            if (gm < M && gk < K) v = TA ? A[gk + gm * lda] : A[gm + gk * lda];
-            As[kk][mm] = v;
-        }
-        // B slice: BK x BN elements of op(B)
-#pragma unroll
-        for (int r = 0; r < (BN * BK) / 256; ++r) {
-            const int e = tid + r * 256;
-            int kk, nn;
-            if (!TB) {
-                kk = e % BK;
-                nn = e / BK;
-            } else {
-                nn = e % BN;
-                kk = e / BN;
-            }
-            const int gn = n0 + nn, gk = k0 + kk;
-            double v = 0.0;
-            if (gn < N && gk < K) v = TB ? B[gn + gk * ldb] : B[gk + gn * ldb];
-            Bs[kk][nn] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-            double a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[ks + lk][wm + i * 16 + li];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = Bs[ks + lk][wn + j * 16 + li];
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-        __syncthreads();
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.a[t][i], cur.b[t][j], acc[i][j], 0, 0, 0);
+        cur = nxt;
     }
 
     // D layout of the 16x16 f64 MFMA (measured on gfx950): lane holds column
     // (lane % 16); its register r holds row (lane / 16) + 4 r.
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wave][(16 * i + lk + 4 * r) + BM * (16 * j + li)] = acc[i][j][r];
+    __syncthreads();
     double *__restrict__ C = d.C;
     const int64_t ldc = d.ldc;
     const double alpha = d.alpha, beta = d.beta;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int gn = n0 + wn + j * 16 + li;
-            if (gn >= N) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm + i * 16 + lk + 4 * r;
-                if (gm >= M) continue;
-                double *c = C + gm + gn * ldc;
-                const double v = alpha * acc[i][j][r];
-                *c = (beta == 0.0) ? v : v + beta * (*c);
-            }
+    for (int e = tid; e < BM * BN; e += 256) {
+        const int r = e % BM, c = e / BM;
+        const int gm = m0 + r, gn = n0 + c;
+        if (gm < M && gn < N) {
+            const double v = alpha * (((red[0][e] + red[1][e]) + red[2][e]) + red[3][e]);
+            double *cp = C + gm + gn * ldc;
+            *cp = (beta == 0.0) ? v : v + beta * (*cp);
         }
+    }
 }
 
 }  // namespace

@@ -140,22 +140,40 @@ __global__ void k_pad_copy(const double *__restrict__ z, int64_t n, int64_t npad
     if (i < npad) out[i] = (i < n) ? z[i] : 0.0;
 }
 
-// y <- L^-1 y for one dense lower-triangular nb x nb tile (one work-group).
+// Wave-uniform broadcast of lane l's double (two v_readlane).
+__device__ inline double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// y <- L^-1 y for one dense lower-triangular nb x nb tile (one work-group),
+// 64 rows at a time: the diagonal block is staged in LDS and solved by one
+// wave (lane r holds y_r; the solved entry is broadcast with readlane), then
+// every thread updates rows below from the block's columns.
 __global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L, int nb,
                                                    double *__restrict__ yv, const DevParams *params) {
+    __shared__ double Db[64 * 65];
     __shared__ double xb[64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (params->status != 0) return;
     for (int b0 = 0; b0 < nb; b0 += 64) {
         const int bs = (nb - b0 < 64) ? nb - b0 : 64;
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int r = e & 63, c = e >> 6;
+            Db[r + 65 * c] = (r < bs && c < bs && r >= c) ? L[(b0 + r) + (int64_t)(b0 + c) * nb] : 0.0;
+        }
+        __syncthreads();
         if (wave == 0) {
             double v = (lane < bs) ? yv[b0 + lane] : 0.0;
             for (int r = 0; r < bs; ++r) {
-                double xr = 0.0;
-                if (lane == r) xr = v / L[(b0 + r) + (int64_t)(b0 + r) * nb];
-                xr = __shfl(xr, r, 64);
-                if (lane == r) v = xr;
-                if (lane > r && lane < bs) v -= L[(b0 + lane) + (int64_t)(b0 + r) * nb] * xr;
+                const double xr = readlane_d(v, r) / Db[r * 66];
+                const double lr = Db[lane + 65 * r];
+                if (lane == r)
+                    v = xr;
+                else if (lane > r)
+                    v -= lr * xr;
             }
             if (lane < bs) {
                 xb[lane] = v;

@@ -1,8 +1,6 @@
 // Batched small dense kernels, one work-group per problem:
-//  * shifted Cholesky of a Gram matrix (shifted CholeskyQR, Fukaya, Kannan,
-//    Nakatsukasa, Zhang, Yamamoto, SIAM J. Sci. Comput. 2020),
-//  * row-wise triangular solves Y <- Y R^-1,
 //  * one-sided (Hestenes) Jacobi SVD of a k x k matrix,
+//  * truncated pivoted QR of a k x k matrix,
 // plus the blocked Cholesky / triangular solve of the dense diagonal tiles.
 #include <algorithm>
 #include <cmath>
@@ -14,12 +12,7 @@ namespace tlr {
 namespace {
 
 constexpr int kSmallThreads = 256;
-constexpr int kLdsK = 124;  // k x k float64 (plus small arrays) fits in LDS up to this k
 constexpr int kJacK = 112;  // Jacobi working copy k x (k+1) plus partial sums
-constexpr int kPackK = 176; // packed lower triangle k(k+1)/2 <= kLdsK^2 doubles
-constexpr int kRegK = 176;  // register-resident pivoted QR (one column per thread)
-constexpr int kCholLds = (kLdsK * kLdsK > kPackK * (kPackK + 1) / 2) ? kLdsK * kLdsK : kPackK * (kPackK + 1) / 2;
-static_assert(kPackK * (kPackK + 1) / 2 <= kCholLds, "packed Cholesky must fit its LDS array");
 
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -88,251 +81,6 @@ __device__ bool chol_inplace(double *W, int ld, int k, double defl, double *part
         __syncthreads();
     }
     return true;
-}
-
-// Cholesky of W (k x k, global, ld) in 64-wide blocks, right-looking: the
-// diagonal block is factored in LDS, the panel below is solved row by row
-// against it in place, and the trailing lower triangle is updated from the
-// panel (all in global memory, which stays in L2 at these sizes).  For k too
-// large to hold W in LDS.  Same deflation rule as chol_inplace.
-__device__ bool chol_blocked_global(double *W, int ld, int k, double defl, double *Lb, double *part, int *s_fail) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int b0 = 0; b0 < k; b0 += 64) {
-        const int bs = (k - b0 < 64) ? k - b0 : 64;
-        for (int e = tid; e < 64 * 64; e += nt) {
-            const int r = e & 63, q = e >> 6;
-            Lb[e] = (r < bs && q < bs) ? W[(b0 + r) + (int64_t)(b0 + q) * ld] : 0.0;
-        }
-        __syncthreads();
-        if (!chol_inplace(Lb, 64, bs, defl, part, s_fail)) return false;
-        for (int e = tid; e < 64 * 64; e += nt) {
-            const int r = e & 63, q = e >> 6;
-            if (r < bs && q < bs && r >= q) W[(b0 + r) + (int64_t)(b0 + q) * ld] = Lb[r + q * 64];
-        }
-        const int rest = k - b0 - bs;
-        if (rest <= 0) break;
-        // panel rows: x L_bb^T = a  (a dead diagonal gives a zero entry)
-        for (int rr = tid; rr < rest; rr += nt) {
-            double *wr = W + (b0 + bs + rr) + (int64_t)b0 * ld;
-            for (int cc = 0; cc < bs; ++cc) {
-                double a = wr[(int64_t)cc * ld];
-                for (int cp = 0; cp < cc; ++cp) a -= wr[(int64_t)cp * ld] * Lb[cc + cp * 64];
-                const double dg = Lb[cc + cc * 64];
-                wr[(int64_t)cc * ld] = (dg != 0.0) ? a / dg : 0.0;
-            }
-        }
-        __syncthreads();
-        // trailing lower triangle: W[r][q] -= sum_c P[r][c] P[q][c]
-        for (int e = tid; e < rest * rest; e += nt) {
-            const int rr = e % rest, qq = e / rest;
-            if (rr < qq) continue;
-            const double *pr = W + (b0 + bs + rr) + (int64_t)b0 * ld;
-            const double *pq = W + (b0 + bs + qq) + (int64_t)b0 * ld;
-            double acc = 0.0;
-            for (int cc = 0; cc < bs; ++cc) acc += pr[(int64_t)cc * ld] * pq[(int64_t)cc * ld];
-            W[(b0 + bs + rr) + (int64_t)(b0 + bs + qq) * ld] -= acc;
-        }
-        __syncthreads();
-    }
-    return true;
-}
-
-// Lower Cholesky with the lower triangle packed by columns in LDS: (r, q),
-// r >= q, at q*k - q(q-1)/2 + (r - q).  Same algorithm and deflation rule as
-// chol_inplace; lets k up to kPackK stay on chip.
-__device__ inline int pk(int r, int q, int k) { return q * k - (q * (q - 1)) / 2 + (r - q); }
-
-__device__ bool chol_packed(double *P, int k, double defl, double *part, int *s_fail) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int half = nt >> 1;
-    const int side = tid / half, lt = tid - side * half;
-    for (int c = 0; c < k; ++c) {
-        const int qs = side ? (c >> 1) : 0, qe = side ? c : (c >> 1);
-        for (int r = c + lt; r < k; r += half) {
-            double acc = 0.0;
-            for (int q = qs; q < qe; ++q) acc += P[pk(r, q, k)] * P[pk(c, q, k)];
-            part[r + side * kMaxSketch] = acc;
-        }
-        __syncthreads();
-        for (int r = c + tid; r < k; r += nt) part[r] = P[pk(r, c, k)] - part[r] - part[r + kMaxSketch];
-        __syncthreads();
-        const double piv = part[c];
-        if (!isfinite(piv) || (defl == 0.0 && !(piv > 0.0))) {
-            if (tid == 0) *s_fail = c + 1;
-            __syncthreads();
-            return false;
-        }
-        if (defl > 0.0 && piv <= defl) {
-            for (int r = c + tid; r < k; r += nt) P[pk(r, c, k)] = 0.0;
-        } else {
-            const double inv = 1.0 / sqrt(piv);
-            for (int r = c + tid; r < k; r += nt) P[pk(r, c, k)] = (r == c) ? sqrt(piv) : part[r] * inv;
-        }
-        __syncthreads();
-    }
-    return true;
-}
-
-__global__ __launch_bounds__(kSmallThreads) void k_chol_small(const SmallDesc *__restrict__ descs,
-                                                               int mode, DevParams *params) {
-    __shared__ double lds[kCholLds];
-    __shared__ double part[2 * kMaxSketch];
-    __shared__ double red[kSmallThreads / 64];
-    __shared__ int s_fail;
-    const SmallDesc d = descs[blockIdx.x];
-    const int k = d.k_dev ? *d.k_dev : d.k;
-    if (k <= 0) return;
-    const int tid = threadIdx.x;
-    const bool packed = (k > kLdsK) && (k <= kPackK);
-    double *W = (k <= kLdsK) ? lds : d.R;
-    const int ldw = (k <= kLdsK) ? k : d.ldr;
-    // mode 1: shifted (shift = 11 (m k + k (k+1)) u ||Y||^2, the squared norm
-    // bounded by the trace);  mode 2: unshifted with deflation of pivots below
-    // 1e-12 of the largest diagonal entry;  mode 0: plain.
-    double shift = 0.0, defl = 0.0;
-    if (mode == 1) {
-        double tr = 0.0;
-        for (int c = tid; c < k; c += blockDim.x) tr += d.A[c + (int64_t)c * d.lda];
-        tr = block_sum(tr, red);
-        shift = 11.0 * ((double)d.m * k + (double)k * (k + 1)) * 1.1102230246251565e-16 * tr;
-        defl = 1e-300;  // an exactly-zero panel (zero tile) deflates instead of failing
-    } else if (mode == 2) {
-        double mx = 0.0;
-        for (int c = tid; c < k; c += blockDim.x) mx = fmax(mx, d.A[c + (int64_t)c * d.lda]);
-        mx = block_max(mx, red);
-        defl = (mx > 0.0) ? 1e-12 * mx : 1e-300;
-    }
-    if (packed) {
-        for (int q = 0; q < k; ++q)
-            for (int r = q + tid; r < k; r += blockDim.x)
-                lds[pk(r, q, k)] = d.A[r + (int64_t)q * d.lda] + ((r == q) ? shift : 0.0);
-    } else {
-        for (int e = tid; e < k * k; e += blockDim.x) {
-            const int r = e % k, q = e / k;
-            if (r >= q) W[r + q * ldw] = d.A[r + (int64_t)q * d.lda] + ((r == q) ? shift : 0.0);
-        }
-    }
-    __syncthreads();
-    bool ok;
-    if (packed) {
-        ok = chol_packed(lds, k, defl, part, &s_fail);
-        if (ok) {
-            for (int e = tid; e < k * k; e += blockDim.x) {
-                const int r = e % k, q = e / k;
-                d.R[r + (int64_t)q * d.ldr] = (r <= q) ? lds[pk(q, r, k)] : 0.0;
-            }
-            return;
-        }
-    } else if (k <= kLdsK) {
-        ok = chol_inplace(W, ldw, k, defl, part, &s_fail);
-    } else {
-        __syncthreads();
-        ok = chol_blocked_global(W, ldw, k, defl, lds, part, &s_fail);
-    }
-    if (!ok) {
-        if (tid == 0) set_status(params, TLR_NOT_SPD, -100 - d.tile_i, -100 - d.tile_j);
-        // leave an identity factor so downstream arithmetic stays finite
-        for (int e = tid; e < k * k; e += blockDim.x) {
-            const int r = e % k, q = e / k;
-            d.R[r + (int64_t)q * d.ldr] = (r == q) ? 1.0 : 0.0;
-        }
-        return;
-    }
-    // R = L^T (upper), zero below the diagonal.  When W aliases R (k > kLdsK)
-    // transpose in place through the upper triangle.
-    if (W == d.R) {
-        for (int e = tid; e < k * k; e += blockDim.x) {
-            const int r = e % k, q = e / k;
-            if (r > q) {
-                W[q + r * ldw] = W[r + q * ldw];
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < k * k; e += blockDim.x) {
-            const int r = e % k, q = e / k;
-            if (r > q) W[r + q * ldw] = 0.0;
-        }
-    } else {
-        for (int e = tid; e < k * k; e += blockDim.x) {
-            const int r = e % k, q = e / k;
-            d.R[r + (int64_t)q * d.ldr] = (r <= q) ? W[q + r * ldw] : 0.0;
-        }
-    }
-}
-
-// ---------------------------------------------------------- row solves --
-
-// Y (m x k) <- Y R^-1 for upper-triangular R.  A work-group of 64 threads
-// owns 64 rows, held transposed in LDS (column c of the block is contiguous,
-// so the 64 lanes read consecutive words); each thread runs the forward
-// substitution of its row, 8 columns at a time in registers.  R is read with
-// wave-uniform addresses.  Panels wider than kTrsmLds columns stay in global
-// memory (same arithmetic).
-constexpr int kTrsmLds = 176;
-
-// Forward substitution of one row y against upper-triangular R, CH columns
-// at a time; the block R[0:c0+CH, c0:c0+CH] is staged in LDS by the whole
-// work-group (one wave) so the inner loop reads it as a broadcast.
-constexpr int kTrsmCh = 8;
-__device__ void row_solve(double *yrow, int64_t stride, int k, const double *__restrict__ R, int64_t ldr,
-                          double *Rb, bool valid) {
-    constexpr int CH = kTrsmCh;
-    const int t = threadIdx.x;
-    for (int c0 = 0; c0 < k; c0 += CH) {
-        const int cw = (k - c0 < CH) ? (k - c0) : CH;
-        const int rows = c0 + cw;
-        __syncthreads();
-        for (int e = t; e < rows * CH; e += blockDim.x) {
-            const int q = e / CH, j = e - q * CH;
-            Rb[e] = (j < cw) ? R[q + (int64_t)(c0 + j) * ldr] : 0.0;
-        }
-        __syncthreads();
-        if (!valid) continue;
-        double acc[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) acc[j] = (j < cw) ? yrow[(c0 + j) * stride] : 0.0;
-        for (int q = 0; q < c0; ++q) {
-            const double v = yrow[q * stride];
-            const double *rq = Rb + q * CH;
-#pragma unroll
-            for (int j = 0; j < CH; ++j) acc[j] -= v * rq[j];
-        }
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            if (j < cw) {
-                double a = acc[j];
-#pragma unroll
-                for (int jp = 0; jp < CH; ++jp)
-                    if (jp < j) a -= acc[jp] * Rb[(c0 + jp) * CH + j];
-                const double rd = Rb[(c0 + j) * CH + j];
-                acc[j] = (rd != 0.0) ? a / rd : 0.0;  // zero diagonal: dead direction
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < CH; ++j)
-            if (j < cw) yrow[(c0 + j) * stride] = acc[j];
-    }
-}
-
-__global__ __launch_bounds__(64) void k_trsm_rows(const SmallDesc *__restrict__ descs) {
-    __shared__ double Yt[kTrsmLds * 64];
-    __shared__ double Rb[kMaxSketch * kTrsmCh];
-    const SmallDesc d = descs[blockIdx.y];
-    const int k = d.k_dev ? *d.k_dev : d.k;
-    const int r0 = blockIdx.x * 64;
-    if (k <= 0 || r0 >= d.m) return;
-    const int t = threadIdx.x;
-    const int row = r0 + t;
-    const bool valid = row < d.m;
-    const int64_t ldy = d.ldy;
-    if (k <= kTrsmLds) {
-        for (int c = 0; c < k; ++c) Yt[c * 64 + t] = valid ? d.Y[row + c * ldy] : 0.0;
-        row_solve(Yt + t, 64, k, d.R, d.ldr, Rb, true);
-        if (valid)
-            for (int c = 0; c < k; ++c) d.Y[row + c * ldy] = Yt[c * 64 + t];
-    } else {
-        row_solve(d.Y + (valid ? row : 0), ldy, k, d.R, d.ldr, Rb, valid);
-    }
 }
 
 // ------------------------------------------------------ one-sided Jacobi --
@@ -566,18 +314,48 @@ __device__ void qrcp_trunc(double *M, int ld, int k, double tol2, double *cn, do
             beta[c] = bta;
         }
         __syncthreads();
-        // apply to the trailing columns and refresh their norms
+        // apply to the trailing columns and refresh their norms; eight rows
+        // at a time so that the loads of a batch are in flight together
         for (int j = c + 1 + tid; j < k; j += THREADS) {
-            double w = 0.0;
-            for (int i = c; i < k; ++i) w += M[i * ld + c] * M[i * ld + j];
+            double w8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int i = c;
+            for (; i + 8 <= k; i += 8) {
+                double vv[8], xx[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    vv[u] = M[(i + u) * ld + c];
+                    xx[u] = M[(i + u) * ld + j];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) w8[u] += vv[u] * xx[u];
+            }
+            for (; i < k; ++i) w8[0] += M[i * ld + c] * M[i * ld + j];
+            double w = ((w8[0] + w8[1]) + (w8[2] + w8[3])) + ((w8[4] + w8[5]) + (w8[6] + w8[7]));
             w *= bta;
-            double s2 = 0.0;
-            for (int i = c; i < k; ++i) {
+            const double nc = M[c * ld + j] - w * M[c * ld + c];
+            M[c * ld + j] = nc;
+            double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            i = c + 1;
+            for (; i + 8 <= k; i += 8) {
+                double vv[8], xx[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    vv[u] = M[(i + u) * ld + c];
+                    xx[u] = M[(i + u) * ld + j];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double nv = xx[u] - w * vv[u];
+                    M[(i + u) * ld + j] = nv;
+                    s8[u] += nv * nv;
+                }
+            }
+            for (; i < k; ++i) {
                 const double nv = M[i * ld + j] - w * M[i * ld + c];
                 M[i * ld + j] = nv;
-                if (i > c) s2 += nv * nv;
+                s8[0] += nv * nv;
             }
-            cn[j] = s2;
+            cn[j] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
         }
         __syncthreads();
         if (tid == 0) red[24] = alpha;
@@ -590,219 +368,245 @@ __device__ void qrcp_trunc(double *M, int ld, int k, double tol2, double *cn, do
     __syncthreads();
 }
 
-// Register-resident variant for kJacK < k <= S*KH, 256*S threads: column j
-// is held in registers by threads j + 256 h, h = 0..S-1, each owning rows
-// [h KH, (h+1) KH); loops are fully unrolled with the row range as a predicate
-// so the arrays stay in VGPRs.  Partial dot products / norms of the S parts
-// meet in LDS.  Same arithmetic as qrcp_trunc.  vstore: k x k global scratch
-// holding the reflectors.
-template <int KH, int S>
-__device__ void qrcp_reg(const SmallDesc &d, int k, double tol2, int min_tail, int k_full, int rank_cap,
-                         DevParams *params, double *vstore) {
-    __shared__ double sv[S * KH];
-    __shared__ double part[S][256], part2[S][256];
-    __shared__ double cn[256];
-    __shared__ double beta[S * KH];
-    __shared__ double alph[S * KH];
-    __shared__ int perm[256];
-    __shared__ double red[24];
-    __shared__ int ired[8];
+// Register-resident variant for k <= 16 RPS and k <= 4 NW CPG (NW waves).
+// The matrix is spread over 4 NW column groups of 16 lanes (a quarter-wave):
+// group g owns columns g + 4 NW cc (cc < CPG), its lane s the rows s + 16 rr
+// (rr < RPS), so a column's reductions are four shuffles inside its group.
+// Columns are never swapped: the pivot of step c is frozen in place (rows < c
+// hold its column of R, row c the diagonal alpha_c) and its Householder
+// vector is kept in V (k x k scratch, column c).  Same arithmetic as
+// qrcp_trunc (pivot = largest remaining norm, smallest index on ties; stop
+// when the remaining Frobenius norm is <= tol), so Y = B^T comes straight from
+// the registers and Q1 is accumulated in registers from V.
+__device__ inline double red16(double v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    return v;
+}
+
+template <int NW, int CPG, int RPS>
+__global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restrict__ descs, double tol,
+                                                        int min_tail, int k_full, int rank_cap, DevParams *params,
+                                                        int kmin) {
+    constexpr int G = 4 * NW, KC = G * CPG, KR = 16 * RPS, NT = NW * 64;
+    constexpr int kNever = 1 << 30;
+    __shared__ double cn[KC];
+    __shared__ int pst[KC];  // step at which the column was pivoted (kNever: not yet)
+    __shared__ double vsh[KR];
+    __shared__ double bet[KR];
+    __shared__ double redv[2 * NW];
+    __shared__ int redi[NW];
+    const SmallDesc d = descs[blockIdx.x];
+    const int k = d.k_dev ? *d.k_dev : d.k;
+    if (k <= 0 && kmin <= 1) {
+        if (threadIdx.x == 0) {
+            d.rank[0] = d.rank[1] = 0;
+            *d.flag = 0;
+        }
+        return;
+    }
+    if (k < kmin || k > KC || k > KR) return;  // another kernel's range
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int j = tid & 255, h = tid >> 8, row0 = h * KH;
-    const bool own = j < k;
-    double col[KH];
+    const int grp = wave * 4 + (lane >> 4), sl = lane & 15;
+    const double tol2 = tol * tol;
+    double *__restrict__ V = d.R;
+    double a[CPG][RPS];
 #pragma unroll
-    for (int ii = 0; ii < KH; ++ii)
-        col[ii] = (own && row0 + ii < k) ? d.A[(row0 + ii) + (int64_t)j * d.lda] : 0.0;
-    {
-        double s2 = 0.0;
+    for (int cc = 0; cc < CPG; ++cc) {
+        const int p = grp + G * cc;
+        double n2 = 0.0;
 #pragma unroll
-        for (int ii = 0; ii < KH; ++ii) s2 += col[ii] * col[ii];
-        part[h][j] = s2;
+        for (int rr = 0; rr < RPS; ++rr) {
+            const int i = sl + 16 * rr;
+            a[cc][rr] = (p < k && i < k) ? d.A[i + (int64_t)p * d.lda] : 0.0;
+            n2 += a[cc][rr] * a[cc][rr];
+        }
+        n2 = red16(n2);
+        if (sl == 0 && p < k) cn[p] = n2;
     }
-    __syncthreads();
-    if (h == 0) {
-        double t = 0.0;
-        for (int q = 0; q < S; ++q) t += part[q][j];
-        cn[j] = own ? t : -1.0;
-        perm[j] = j;
-    }
+    for (int t = tid; t < KC; t += NT) pst[t] = kNever;
     __syncthreads();
     int c = 0;
     for (; c < k; ++c) {
-        if (h == 0) {
-            const bool act = own && j >= c;
-            double rem = act ? cn[j] : 0.0, best = act ? cn[j] : -1.0;
-            int bj = act ? j : k;
-            for (int off = 32; off > 0; off >>= 1) {
-                rem += __shfl_xor(rem, off, 64);
-                const double ob = __shfl_xor(best, off, 64);
-                const int oj = __shfl_xor(bj, off, 64);
-                if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
-            }
-            if (lane == 0) { red[wave] = rem; red[8 + wave] = best; ired[wave] = bj; }
-        }
-        __syncthreads();
         double rem = 0.0, best = -1.0;
         int bj = k;
-        for (int w = 0; w < 4; ++w) {
-            rem += red[w];
-            if (red[8 + w] > best || (red[8 + w] == best && ired[w] < bj)) { best = red[8 + w]; bj = ired[w]; }
+        if (tid < k && pst[tid] == kNever) {
+            rem = cn[tid];
+            best = cn[tid];
+            bj = tid;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            rem += __shfl_xor(rem, off, 64);
+            const double ob = __shfl_xor(best, off, 64);
+            const int oj = __shfl_xor(bj, off, 64);
+            if (ob > best || (ob == best && oj < bj)) {
+                best = ob;
+                bj = oj;
+            }
+        }
+        if (lane == 0) {
+            redv[wave] = rem;
+            redv[NW + wave] = best;
+            redi[wave] = bj;
+        }
+        __syncthreads();
+        rem = 0.0;
+        best = -1.0;
+        bj = k;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            rem += redv[w];
+            if (redv[NW + w] > best || (redv[NW + w] == best && redi[w] < bj)) {
+                best = redv[NW + w];
+                bj = redi[w];
+            }
         }
         if (rem <= tol2) break;
-        __syncthreads();
-        if (bj != c) {  // swap columns c and bj through LDS, both halves
-            if (j == bj) {
+        // Householder vector of column bj, by the group that owns it
+        if (grp == bj % G) {
+            const int oc = bj / G;
+            double x2 = 0.0, x0 = 0.0;
 #pragma unroll
-                for (int ii = 0; ii < KH; ++ii) sv[row0 + ii] = col[ii];
-            }
-            __syncthreads();
-            if (j == c) {
+            for (int cc = 0; cc < CPG; ++cc)
+                if (cc == oc) {
 #pragma unroll
-                for (int ii = 0; ii < KH; ++ii) {
-                    const double t = col[ii];
-                    col[ii] = sv[row0 + ii];
-                    sv[row0 + ii] = t;
+                    for (int rr = 0; rr < RPS; ++rr) {
+                        const int i = sl + 16 * rr;
+                        if (i == c) x0 = a[cc][rr];
+                        if (i > c && i < k) x2 += a[cc][rr] * a[cc][rr];
+                    }
                 }
-            }
-            __syncthreads();
-            if (j == bj) {
-#pragma unroll
-                for (int ii = 0; ii < KH; ++ii) col[ii] = sv[row0 + ii];
-            }
-            if (tid == 0) {
-                const double t = cn[c]; cn[c] = cn[bj]; cn[bj] = t;
-                const int q = perm[c]; perm[c] = perm[bj]; perm[bj] = q;
-            }
-            __syncthreads();
-        }
-        // Householder vector of column c: partial sums of both halves
-        if (j == c) {
-            double x2 = 0.0, x0 = 0.0;
-#pragma unroll
-            for (int ii = 0; ii < KH; ++ii) {
-                const int i = row0 + ii;
-                if (i == c) x0 = col[ii];
-                if (i > c) x2 += col[ii] * col[ii];
-            }
-            part[h][0] = x2;
-            part2[h][0] = x0;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double x2 = 0.0, x0 = 0.0;
-            for (int q = 0; q < S; ++q) {
-                x2 += part[q][0];
-                x0 += part2[q][0];
-            }
+            x2 = red16(x2);
+            x0 = red16(x0);
             const double nrm = sqrt(x0 * x0 + x2);
             const double alpha = (x0 > 0.0) ? -nrm : nrm;
             const double v0 = x0 - alpha;
             const double vtv = v0 * v0 + x2;
-            beta[c] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-            alph[c] = alpha;
-            red[16] = v0;
-        }
-        __syncthreads();
-        if (j == c) {
-            const double v0 = red[16];
 #pragma unroll
-            for (int ii = 0; ii < KH; ++ii) {
-                const int i = row0 + ii;
-                const double vi = (i < c) ? 0.0 : (i == c ? v0 : col[ii]);
-                sv[i] = vi;
-                if (i < k) vstore[i + (int64_t)c * k] = vi;
+            for (int cc = 0; cc < CPG; ++cc)
+                if (cc == oc) {
+#pragma unroll
+                    for (int rr = 0; rr < RPS; ++rr) {
+                        const int i = sl + 16 * rr;
+                        const double vi = (i < c || i >= k) ? 0.0 : ((i == c) ? v0 : a[cc][rr]);
+                        vsh[i] = vi;
+                        if (i < k) V[i + (int64_t)c * k] = vi;
+                        if (i == c) a[cc][rr] = alpha;
+                    }
+                }
+            if (sl == 0) {
+                bet[c] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+                pst[bj] = c;
             }
         }
         __syncthreads();
-        const bool upd = own && j > c;
-        if (upd) {
-            double w = 0.0;
+        const double bta = bet[c];
+        double vr[RPS];
 #pragma unroll
-            for (int ii = 0; ii < KH; ++ii) w += sv[row0 + ii] * col[ii];
-            part[h][j] = w;
-        }
-        __syncthreads();
-        if (upd) {
-            double w = 0.0;
-            for (int q = 0; q < S; ++q) w += part[q][j];
-            w *= beta[c];
-            double s2 = 0.0;
+        for (int rr = 0; rr < RPS; ++rr) vr[rr] = vsh[sl + 16 * rr];
+        double w[CPG];
+        bool act[CPG];
 #pragma unroll
-            for (int ii = 0; ii < KH; ++ii) {
-                col[ii] -= w * sv[row0 + ii];
-                if (row0 + ii > c) s2 += col[ii] * col[ii];
-            }
-            part2[h][j] = s2;
-        }
-        __syncthreads();
-        if (h == 0 && upd) {
+        for (int cc = 0; cc < CPG; ++cc) {
+            const int p = grp + G * cc;
+            act[cc] = p < k && pst[p] == kNever;
             double t = 0.0;
-            for (int q = 0; q < S; ++q) t += part2[q][j];
-            cn[j] = t;
+#pragma unroll
+            for (int rr = 0; rr < RPS; ++rr) t += vr[rr] * a[cc][rr];
+            w[cc] = act[cc] ? t : 0.0;
+        }
+#pragma unroll
+        for (int cc = 0; cc < CPG; ++cc) w[cc] = red16(w[cc]) * bta;
+#pragma unroll
+        for (int cc = 0; cc < CPG; ++cc) {
+            double n2 = 0.0;
+#pragma unroll
+            for (int rr = 0; rr < RPS; ++rr) {
+                const int i = sl + 16 * rr;
+                a[cc][rr] -= w[cc] * vr[rr];
+                if (i > c && i < k) n2 += a[cc][rr] * a[cc][rr];
+            }
+            w[cc] = n2;
+        }
+#pragma unroll
+        for (int cc = 0; cc < CPG; ++cc) {
+            const double n2 = red16(w[cc]);
+            if (act[cc] && sl == 0) cn[grp + G * cc] = n2;
         }
         __syncthreads();
     }
-    const int rr = c;
-    const int insufficient = (k - rr < min_tail) && (k < (d.k_full < k_full ? d.k_full : k_full));
-    int r = insufficient ? 0 : rr;
+    const int rr_rank = c;
+    const int insufficient = (k - rr_rank < min_tail) && (k < (d.k_full < k_full ? d.k_full : k_full));
+    int r = insufficient ? 0 : rr_rank;
     if (!insufficient && r > rank_cap) {
         if (tid == 0) set_status(params, TLR_RANK_OVERFLOW, d.tile_i, d.tile_j);
         r = rank_cap;
     }
-    // B^T: column j of R (rows < r) goes to Y[perm[j], :]
-    if (own) {
+    // Y = B^T: B[i][p] = R entry for i <= pivot step of p (the diagonal sits
+    // at the pivot step), 0 below
 #pragma unroll
-        for (int ii = 0; ii < KH; ++ii) {
-            const int i = row0 + ii;
-            if (i < r) {
-                const double v = (i < j) ? col[ii] : (i == j ? alph[i] : 0.0);
-                d.Y[perm[j] + (int64_t)i * d.ldy] = v;
+    for (int cc = 0; cc < CPG; ++cc) {
+        const int p = grp + G * cc;
+        if (p < k) {
+            const int ps = pst[p];
+#pragma unroll
+            for (int rr = 0; rr < RPS; ++rr) {
+                const int i = sl + 16 * rr;
+                if (i < r) d.Y[p + (int64_t)i * d.ldy] = (i <= ps) ? a[cc][rr] : 0.0;
             }
         }
     }
-    // Q1 = H_0 ... H_{r-1} [I_r; 0]: column q in the registers of threads q, q+256
-    double qc[KH];
+    __syncthreads();  // reflectors in V visible to every wave
+    // Q1 = H_0 ... H_{r-1} [I_r; 0]: column q held like matrix column q
 #pragma unroll
-    for (int ii = 0; ii < KH; ++ii) qc[ii] = (row0 + ii == j) ? 1.0 : 0.0;
-    for (int cc = r - 1; cc >= 0; --cc) {
-        __syncthreads();
-        for (int i = tid; i < S * KH; i += 256 * S) sv[i] = (i < k) ? vstore[i + (int64_t)cc * k] : 0.0;
-        __syncthreads();
-        if (j < r) {
-            double w = 0.0;
+    for (int cc = 0; cc < CPG; ++cc) {
+        const int q = grp + G * cc;
 #pragma unroll
-            for (int ii = 0; ii < KH; ++ii) w += sv[row0 + ii] * qc[ii];
-            part[h][j] = w;
+        for (int rr = 0; rr < RPS; ++rr) a[cc][rr] = (sl + 16 * rr == q) ? 1.0 : 0.0;
+    }
+    for (int h = r - 1; h >= 0; --h) {
+        double vr[RPS];
+#pragma unroll
+        for (int rr = 0; rr < RPS; ++rr) {
+            const int i = sl + 16 * rr;
+            vr[rr] = (i >= h && i < k) ? V[i + (int64_t)h * k] : 0.0;
         }
-        __syncthreads();
-        if (j < r) {
-            double w = 0.0;
-            for (int q = 0; q < S; ++q) w += part[q][j];
-            w *= beta[cc];
+        const double bt = bet[h];
 #pragma unroll
-            for (int ii = 0; ii < KH; ++ii) qc[ii] -= w * sv[row0 + ii];
+        for (int cc = 0; cc < CPG; ++cc) {
+            const int q = grp + G * cc;
+            double t = 0.0;
+#pragma unroll
+            for (int rr = 0; rr < RPS; ++rr) t += vr[rr] * a[cc][rr];
+            t = red16(t) * bt;
+            if (q < r && q >= h) {
+#pragma unroll
+                for (int rr = 0; rr < RPS; ++rr) a[cc][rr] -= t * vr[rr];
+            }
         }
     }
-    if (j < r) {
 #pragma unroll
-        for (int ii = 0; ii < KH; ++ii)
-            if (row0 + ii < k) d.X[(row0 + ii) + (int64_t)j * d.ldx] = qc[ii];
+    for (int cc = 0; cc < CPG; ++cc) {
+        const int q = grp + G * cc;
+        if (q < r) {
+#pragma unroll
+            for (int rr = 0; rr < RPS; ++rr) {
+                const int i = sl + 16 * rr;
+                if (i < k) d.X[i + (int64_t)q * d.ldx] = a[cc][rr];
+            }
+        }
     }
     if (tid == 0) {
         d.rank[0] = r;
-        d.rank[1] = rr;
+        d.rank[1] = rr_rank;
         *d.flag = insufficient;
     }
 }
 
-__global__ __launch_bounds__(1024) void k_qrcp_reg(const SmallDesc *__restrict__ descs, double tol, int min_tail,
-                                                    int k_full, int rank_cap, DevParams *params) {
-    const SmallDesc d = descs[blockIdx.x];
-    const int k = d.k_dev ? *d.k_dev : d.k;
-    if (k <= kJacK || k > kRegK) return;  // handled by k_qrcp_trunc
-    qrcp_reg<kRegK / 4, 4>(d, k, tol * tol, min_tail, k_full, rank_cap, params, d.R);
-}
+constexpr int kQrSmallK = 64;   // k_qrcp_regs<4, 4, 4>
+constexpr int kQrMidK = 192;    // k_qrcp_regs<8, 6, 12>
 
 __global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict__ descs, double tol, int min_tail,
                                                      int k_full, int rank_cap, DevParams *params) {
@@ -824,7 +628,7 @@ __global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict_
         }
         return;
     }
-    if (k > kJacK && k <= kRegK) return;  // k_qrcp_reg
+    if (k <= kQrMidK) return;  // k_qrcp_regs
     double *M = (k <= kJacK) ? lds : d.R;  // row-major working copy
     const int ldm = (k <= kJacK) ? k + 1 : k;
     for (int e = tid; e < k * k; e += 256) {
@@ -859,11 +663,34 @@ __global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict_
     for (int c = r - 1; c >= 0; --c) {
         const double bta = beta[c];
         for (int q = tid; q < r; q += 256) {
+            // eight rows at a time so that a batch's loads are in flight together
             double *xq = d.X + (int64_t)q * d.ldx;
-            double w = 0.0;
-            for (int i = c; i < k; ++i) w += M[i * ldm + c] * xq[i];
-            w *= bta;
-            for (int i = c; i < k; ++i) xq[i] -= w * M[i * ldm + c];
+            double w8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int i = c;
+            for (; i + 8 <= k; i += 8) {
+                double vv[8], xx[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    vv[u] = M[(i + u) * ldm + c];
+                    xx[u] = xq[i + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) w8[u] += vv[u] * xx[u];
+            }
+            for (; i < k; ++i) w8[0] += M[i * ldm + c] * xq[i];
+            const double w = bta * (((w8[0] + w8[1]) + (w8[2] + w8[3])) + ((w8[4] + w8[5]) + (w8[6] + w8[7])));
+            i = c;
+            for (; i + 8 <= k; i += 8) {
+                double vv[8], xx[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    vv[u] = M[(i + u) * ldm + c];
+                    xx[u] = xq[i + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xq[i + u] = xx[u] - w * vv[u];
+            }
+            for (; i < k; ++i) xq[i] -= w * M[i * ldm + c];
         }
         __syncthreads();
     }
@@ -963,42 +790,6 @@ __global__ __launch_bounds__(64) void k_trsm_block(const double *__restrict__ L,
 
 }  // namespace
 
-tlr_status chol_small(const SmallDesc *d_descs, int count, int max_k, int mode, DevParams *params,
-                      hipStream_t s, const SmallDesc *h_descs) {
-    (void)max_k;
-    if (count <= 0) return TLR_OK;
-    static const int cls = ktimer_class("k_chol_small");
-    double flops = 0.0, bytes = 0.0;
-    if (h_descs && ktimer_on())
-        for (int t = 0; t < count; ++t) {
-            const double k = h_descs[t].k;
-            flops += k * k * k / 3.0;
-            bytes += 8.0 * k * (k + 1.0);  // lower triangle in, upper factor out
-        }
-    KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
-    hipLaunchKernelGGL(k_chol_small, dim3(count), dim3(kSmallThreads), 0, s, d_descs, mode, params);
-    TLR_HIP(hipGetLastError());
-    return TLR_OK;
-}
-
-tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, hipStream_t s,
-                     const SmallDesc *h_descs) {
-    (void)max_k;
-    if (count <= 0 || max_m <= 0) return TLR_OK;
-    static const int cls = ktimer_class("k_trsm_rows");
-    double flops = 0.0, bytes = 0.0;
-    if (h_descs && ktimer_on())
-        for (int t = 0; t < count; ++t) {
-            const double k = h_descs[t].k, m = h_descs[t].m;
-            flops += m * k * k;
-            bytes += 8.0 * (2.0 * m * k + k * (k + 1.0) / 2.0);
-        }
-    KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
-    hipLaunchKernelGGL(k_trsm_rows, dim3((unsigned)cdiv(max_m, 64), count), dim3(64), 0, s, d_descs);
-    TLR_HIP(hipGetLastError());
-    return TLR_OK;
-}
-
 tlr_status jacobi_svd(const SmallDesc *d_descs, int count, int max_k, double tol, int min_tail,
                       int k_full, int rank_cap, DevParams *params, hipStream_t s) {
     (void)max_k;
@@ -1014,16 +805,22 @@ tlr_status jacobi_svd(const SmallDesc *d_descs, int count, int max_k, double tol
 tlr_status qrcp_trunc(const SmallDesc *d_descs, int count, int max_k, double tol, int min_tail, int k_full,
                       int rank_cap, DevParams *params, hipStream_t s) {
     if (count <= 0) return TLR_OK;
-    static const int cls_t = ktimer_class("k_qrcp_trunc"), cls_r = ktimer_class("k_qrcp_reg");
+    static const int cls_s = ktimer_class("k_qrcp_regs<4,4,4>"), cls_m = ktimer_class("k_qrcp_regs<8,6,12>"),
+                     cls_t = ktimer_class("k_qrcp_trunc");
+    // the stopping step (the rank) is decided on the device: no fixed count
     {
-        // the stopping step (the rank) is decided on the device
+        KTimer kt(cls_s, s, 0.0, 0.0, false);
+        hipLaunchKernelGGL((k_qrcp_regs<4, 4, 4>), dim3(count), dim3(256), 0, s, d_descs, tol, min_tail, k_full,
+                           rank_cap, params, 1);
+    }
+    if (max_k > kQrSmallK) {
+        KTimer kt(cls_m, s, 0.0, 0.0, false);
+        hipLaunchKernelGGL((k_qrcp_regs<8, 6, 12>), dim3(count), dim3(512), 0, s, d_descs, tol, min_tail, k_full,
+                           rank_cap, params, kQrSmallK + 1);
+    }
+    if (max_k > kQrMidK) {
         KTimer kt(cls_t, s, 0.0, 0.0, false);
         hipLaunchKernelGGL(k_qrcp_trunc, dim3(count), dim3(256), 0, s, d_descs, tol, min_tail, k_full, rank_cap,
-                           params);
-    }
-    if (max_k > kJacK) {
-        KTimer kt(cls_r, s, 0.0, 0.0, false);
-        hipLaunchKernelGGL(k_qrcp_reg, dim3(count), dim3(1024), 0, s, d_descs, tol, min_tail, k_full, rank_cap,
                            params);
     }
     TLR_HIP(hipGetLastError());

@@ -261,6 +261,7 @@ tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int pa
             d.lda = jb.k;
             d.R = jb.Rp[it];
             d.ldr = jb.k;
+            d.X = jb.T;  // k x k scratch for the Cholesky tiles when they exceed LDS
             d.Y = Yp;
             d.ldy = nb;
             d.m = nb;
@@ -404,7 +405,7 @@ int clamp_k(const tlr_plan_s *p, int want, int kfull) {
 
 // Smallest ladder width >= want (see widen_k).
 int ladder_k(const tlr_plan_s *p, int want, int kfull) {
-    static const int ladder[] = {32, 64, 112, 176, 240, 320, 400, 512};
+    static const int ladder[] = {32, 64, 112, 176, 192, 240, 320, 400, 512};
     int k = want;
     for (int w : ladder)
         if (w >= want) {
@@ -417,7 +418,7 @@ int ladder_k(const tlr_plan_s *p, int want, int kfull) {
 // Next sketch width after a too-narrow sample: a fixed ladder that stays at
 // the widths the small kernels handle in LDS as long as possible.
 int widen_k(const tlr_plan_s *p, int k, int kfull) {
-    static const int ladder[] = {32, 64, 112, 176, 240, 320, 400, 512};
+    static const int ladder[] = {32, 64, 112, 176, 192, 240, 320, 400, 512};
     int next = 2 * k;
     for (int w : ladder)
         if (w > k) {

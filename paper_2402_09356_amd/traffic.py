@@ -1,0 +1,112 @@
+"""HBM traffic per kernel launch from rocprofv3 counter passes.
+
+Two counter passes of the same command -- one collecting FETCH_SIZE, one
+WRITE_SIZE (KiB per dispatch) -- are reduced to mean KiB per launch for
+every kernel.  The command also runs one plain device-to-device copy of a
+known size (``bench.py --copy-probe-mib``); the ratio of its known bytes to
+what the counters report for it calibrates the counters, and that factor
+scales every kernel's figure.
+
+    python -m paper_2402_09356_amd.traffic --fetch DIR --write DIR \\
+        --copy-mib 1024 --workload "..." --out profiles/traffic.json
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2402_09356_amd", "csrc")
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def short_name(kernel: str) -> str:
+    """Kernel class name as the launch timer reports it (mangled or
+    demangled symbol in, e.g. "k_gemm_f64<T,N>" out)."""
+    m = re.search(r"k_gemm_f64ILb(\d)ELb(\d)E", kernel)
+    if m:
+        ta, tb = m.group(1) == "1", m.group(2) == "1"
+        return "k_gemm_f64<%s,%s>" % ("T" if ta else "N", "T" if tb else "N")
+    m = re.search(r"k_gemm_f64<(true|false), ?(true|false)>", kernel)
+    if m:
+        return "k_gemm_f64<%s,%s>" % ("T" if m.group(1) == "true" else "N", "T" if m.group(2) == "true" else "N")
+    m = re.search(r"(k_[a-z][a-z_0-9]*)", kernel)
+    return m.group(1) if m else kernel.split("(")[0][:60]
+
+
+def read_counter(dirpath: str, counter: str):
+    """{kernel name: [value per dispatch]} for one counter."""
+    files = glob.glob(os.path.join(dirpath, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {dirpath}")
+    per = defaultdict(dict)
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = (f, row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                per[row["Kernel_Name"]][key] = per[row["Kernel_Name"]].get(key, 0.0) + float(row["Counter_Value"])
+    return {k: list(v.values()) for k, v in per.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-mib", type=float, required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--command", required=True, help="command line the passes profiled")
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    fetch = read_counter(args.fetch, "FETCH_SIZE")
+    write = read_counter(args.write, "WRITE_SIZE")
+    copy_bytes = args.copy_mib * 2**20
+    copy_names = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
+    # the probe is the one copy dispatch whose fetch is closest to its size
+    best = None
+    for k in copy_names:
+        for v in fetch[k]:
+            if best is None or abs(v * 1024 - copy_bytes) < abs(best[1] * 1024 - copy_bytes):
+                best = (k, v)
+    if best is None:
+        raise SystemExit("copy probe not found in the FETCH_SIZE pass")
+    wbest = min((v for v in write.get(best[0], [])), key=lambda v: abs(v * 1024 - copy_bytes), default=None)
+    f_fetch = copy_bytes / (best[1] * 1024)
+    f_write = copy_bytes / (wbest * 1024) if wbest else None
+    kernels = {}
+    for k, vals in fetch.items():
+        name = short_name(k)
+        if name in kernels or not name.startswith("k_"):
+            continue
+        fv = [v for kk, vv in fetch.items() if short_name(kk) == name for v in vv]
+        wv = [v for kk, vv in write.items() if short_name(kk) == name for v in vv]
+        mf = sum(fv) / len(fv) * 1024 * f_fetch
+        mw = (sum(wv) / len(wv) * 1024 * f_write) if (wv and f_write) else 0.0
+        kernels[name] = {"dispatches": len(fv), "fetch_bytes_per_launch": mf, "write_bytes_per_launch": mw,
+                         "hbm_bytes_per_launch": mf + mw}
+    rec = {"workload": args.workload, "source_sha256": source_digest(), "command": args.command,
+           "copy_probe": {"kernel": best[0][:80], "bytes": copy_bytes, "fetch_kib": best[1], "write_kib": wbest,
+                          "fetch_factor": f_fetch, "write_factor": f_write},
+           "kernels": kernels}
+    with open(args.out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({"copy_probe": rec["copy_probe"], "kernels": len(kernels)}))
+
+
+if __name__ == "__main__":
+    main()

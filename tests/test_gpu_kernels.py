@@ -93,7 +93,7 @@ def test_cholqr_rank_deficient_panel(k):
     np.testing.assert_allclose(sr, sy, rtol=0, atol=1e-13 * sy[0])
 
 
-@pytest.mark.parametrize("k", [16, 64, 112, 113, 150, 176, 200])
+@pytest.mark.parametrize("k", [16, 64, 65, 112, 113, 150, 176, 192, 193, 240])
 def test_qrcp_truncation(k):
     """Truncated pivoted QR: ||A - Q1 B||_2 <= tol, Q1 orthonormal, rank at
     least the singular-value rank and equal (up to a pivot tie) to the first
