@@ -182,9 +182,18 @@ __global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L,
         }
         __syncthreads();
         for (int row = b0 + bs + tid; row < nb; row += blockDim.x) {
-            double acc = 0.0;
-            for (int c = 0; c < bs; ++c) acc += L[row + (int64_t)(b0 + c) * nb] * xb[c];
-            yv[row] -= acc;
+            // eight columns at a time so that a batch's loads are in flight together
+            double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int c = 0;
+            for (; c + 8 <= bs; c += 8) {
+                double lv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) lv[u] = L[row + (int64_t)(b0 + c + u) * nb];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a8[u] += lv[u] * xb[c + u];
+            }
+            for (; c < bs; ++c) a8[0] += L[row + (int64_t)(b0 + c) * nb] * xb[c];
+            yv[row] -= ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
         }
         __syncthreads();
     }
