@@ -12,15 +12,16 @@
 // stays in L2.  k is padded to a multiple of 16 with an identity block.
 //
 // One step b of the factorisation:
-//   1. one wave factors the diagonal tile in registers (lane r holds row r,
-//      columns meet through cross-lane shuffles);
+//   1. one wave factors the diagonal tile in registers (lane r holds row r;
+//      the pivot comes by readlane, each new column goes round through LDS);
 //   2. every row of the panel below is solved against it (one thread a row);
 //   3. every trailing tile (i, j), b < j <= i, takes A_ij -= L_ib L_jb^T with
 //      four v_mfma_f64_16x16x4 (one wave a tile).
-// Pivot rule (same as the unblocked algorithm in exact arithmetic): a pivot
-// that is not finite fails; with defl == 0 a pivot <= 0 fails; with defl > 0
-// a pivot <= defl is a dead direction whose whole column of L is zero, so the
-// row solve writes a zero column of Q there.
+// Pivot rule: a pivot that is not finite fails; with defl == 0 (dense
+// diagonal tiles) a pivot <= 1e-14 of its value at the start of its 16-column
+// step fails (singular to working precision); with defl > 0 a pivot <= defl
+// is a dead direction whose whole column of L is zero, so the row solve
+// writes a zero column of Q there.
 #include <cmath>
 
 #include "kernels.h"
@@ -33,11 +34,23 @@ constexpr int kT = 16;
 constexpr int kTP = 17;
 constexpr int kTW = kT * kTP;
 constexpr int kCholLdsTiles = 11;
+// Plain mode (dense diagonal tiles): a pivot that keeps no more than this
+// fraction of its value at the start of its 16-column step is numerically
+// zero, i.e. the matrix is singular to working precision.
+constexpr double kPivotLoss = 1e-14;
 constexpr int kThreads = 256;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __host__ inline int tri(int i) { return i * (i + 1) / 2; }
+
+// Broadcast of lane l's double to the whole wave (two v_readlane; l uniform).
+__device__ inline double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -51,8 +64,10 @@ __device__ inline double wave_max(double v) {
 
 // Factor the tiles in TS (tile rows T); returns the failing column + 1, or 0.
 template <bool LDS>
-__device__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, int *s_fail) {
+__device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, int *s_fail) {
+    __shared__ double colb[64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll 1
     for (int b = 0; b < T; ++b) {
         // 1. diagonal tile
         if (wave == 0) {
@@ -61,16 +76,17 @@ __device__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, in
             double a[kT];
 #pragma unroll
             for (int q = 0; q < kT; ++q) a[q] = D[r + kTP * q];
+            const double dstart = D[r + kTP * r];  // this row's diagonal entry before the tile's steps
             int fail = 0;
 #pragma unroll
             for (int c = 0; c < kT; ++c) {
-                const double piv = __shfl(a[c], c, 64);
+                const double piv = readlane_d(a[c], c);
                 const int gc = kT * b + c;
                 double lcc, iv;
                 if (gc >= k) {  // padding
                     lcc = 1.0;
                     iv = 1.0;
-                } else if (!isfinite(piv) || (defl == 0.0 && !(piv > 0.0))) {
+                } else if (!isfinite(piv) || (defl == 0.0 && !(piv > kPivotLoss * readlane_d(dstart, c)))) {
                     if (!fail) fail = gc + 1;
                     lcc = 0.0;
                     iv = 0.0;
@@ -78,13 +94,21 @@ __device__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, in
                     lcc = 0.0;  // dead direction
                     iv = 0.0;
                 } else {
-                    lcc = sqrt(piv);
-                    iv = 1.0 / lcc;
+                    iv = rsqrt(piv);
+                    lcc = piv * iv;
                 }
                 const double lrc = (r == c) ? lcc : ((r > c) ? a[c] * iv : 0.0);
                 a[c] = lrc;
+                // the column goes through LDS (one write, all reads in flight
+                // together); LDS operations of one wave complete in order
+                colb[lane] = lrc;
+                __builtin_amdgcn_wave_barrier();
+                double lq[kT];
 #pragma unroll
-                for (int q = c + 1; q < kT; ++q) a[q] -= lrc * __shfl(lrc, q, 64);
+                for (int q = c + 1; q < kT; ++q) lq[q] = colb[q];
+#pragma unroll
+                for (int q = c + 1; q < kT; ++q) a[q] -= lrc * lq[q];
+                __builtin_amdgcn_wave_barrier();
                 if (lane == c) inv[c] = iv;
             }
             if (lane < kT) {
@@ -99,6 +123,7 @@ __device__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, in
         if (n == 0) break;
         // 2. panel rows: x L_bb^T = a
         const double *D = TS + (tri(b) + b) * kTW;
+#pragma unroll 1
         for (int rr = tid; rr < kT * n; rr += kThreads) {
             const int ti = b + 1 + (rr >> 4), r = rr & 15;
             double *P = TS + (tri(ti) + b) * kTW;
@@ -119,6 +144,7 @@ __device__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, in
         // 3. trailing tiles
         const int count = tri(n);
         const int li = lane & 15, lg = lane >> 4;
+#pragma unroll 1
         for (int t = wave; t < count; t += kThreads / 64) {
             int ip = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
             while (tri(ip + 1) <= t) ++ip;
@@ -145,9 +171,10 @@ __device__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, in
 }
 
 template <bool LDS>
-__device__ void load_tiles(double *TS, int T, int k, const double *A, int64_t lda, double shift) {
+__device__ __forceinline__ void load_tiles(double *TS, int T, int k, const double *A, int64_t lda, double shift) {
     const int tid = threadIdx.x;
     const int r = tid & 15, c = tid >> 4;  // 256 threads: one tile per pass
+#pragma unroll 1
     for (int ti = 0, t = 0; ti < T; ++ti)
         for (int tj = 0; tj <= ti; ++tj, ++t) {
             const int gr = kT * ti + r, gc = kT * tj + c;
@@ -160,7 +187,7 @@ __device__ void load_tiles(double *TS, int T, int k, const double *A, int64_t ld
         }
 }
 
-__device__ void store_r(const double *TS, int k, double *R, int64_t ldr) {
+__device__ __forceinline__ void store_r(const double *TS, int k, double *R, int64_t ldr) {
     for (int e = threadIdx.x; e < k * k; e += kThreads) {
         const int r = e % k, q = e / k;
         double v = 0.0;
@@ -263,11 +290,19 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restr
         }
         const int arow = rowbase + li;
         const bool arow_ok = arow < m;
-        for (int s = 0; s < 4 * b; ++s) {
-            const int kap = 4 * s + lg;
-            const double av = arow_ok ? -Y[arow + (int64_t)kap * ldy] : 0.0;
-            const double bv = Rb[kap * kTP + li];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        // eight K-steps at a time: their operand loads are issued together
+        for (int s0 = 0; s0 < 4 * b; s0 += 8) {
+            double av[8], bv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kap = 4 * (s0 + u) + lg;
+                const bool in = s0 + u < 4 * b;
+                av[u] = (in && arow_ok) ? -Y[arow + (int64_t)kap * ldy] : 0.0;
+                bv[u] = in ? Rb[kap * kTP + li] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (s0 + u < 4 * b) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
         }
         const double *Rd = Rb + (kT * b) * kTP;  // rows 16b.. of the staged block
 #pragma unroll
@@ -277,6 +312,7 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restr
             const double rjl = Rd[j * kTP + li];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
+                // x_j of this lane's row: column j sits in lane 16 g + j of row group g
                 const double x = __shfl(acc[q] * iv, (lane & 48) + j, 64);
                 if (li == j)
                     acc[q] = x;
@@ -292,7 +328,90 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restr
     }
 }
 
+// Cholesky of one bs x bs diagonal block A[b0:b0+bs, b0:b0+bs] (ld) of a
+// dense diagonal tile, in LDS with the tile algorithm above (plain pivots: a
+// pivot <= 0 fails with TLR_NOT_SPD for the tile).
+__global__ __launch_bounds__(kThreads) void k_potrf_block(double *A, int ld, int b0, int bs, int tile,
+                                                           DevParams *params) {
+    constexpr int TB = 4;  // 64 = 4 tiles
+    __shared__ double ts[(TB * (TB + 1) / 2) * kTW];
+    __shared__ double inv[kT];
+    __shared__ int s_fail;
+    if (params->status != 0) return;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_fail = 0;
+    const int T = (bs + kT - 1) / kT;
+    double *Ab = A + b0 + (int64_t)b0 * ld;
+    load_tiles<true>(ts, T, bs, Ab, ld, 0.0);
+    __syncthreads();
+    const int fail = chol_tiles<true>(ts, T, bs, 0.0, inv, &s_fail);
+    if (fail) {
+        if (tid == 0) set_status(params, TLR_NOT_SPD, tile, tile);
+        return;
+    }
+    for (int e = tid; e < bs * bs; e += kThreads) {
+        const int r = e % bs, q = e / bs;
+        if (r >= q) Ab[r + (int64_t)q * ld] = ts[(tri(r >> 4) + (q >> 4)) * kTW + (r & 15) + kTP * (q & 15)];
+    }
+}
+
+// Rows r in [b0+bs, nrows): A[r, b0:b0+bs] <- A[r, b0:b0+bs] L_bb^-T, one row
+// per thread.
+__global__ __launch_bounds__(kThreads) void k_potrf_panel(double *A, int ld, int b0, int bs, int nrows,
+                                                           DevParams *params) {
+    __shared__ double L[64 * 65];
+    const int tid = threadIdx.x;
+    if (params->status != 0) return;
+    for (int e = tid; e < 64 * 64; e += kThreads) {
+        const int r = e & 63, q = e >> 6;
+        L[r + q * 65] = (r < bs && q < bs && r >= q) ? A[(b0 + r) + (int64_t)(b0 + q) * ld] : 0.0;
+    }
+    __syncthreads();
+    const int row = b0 + bs + blockIdx.x * kThreads + tid;
+    if (row >= nrows) return;
+    double x[64];
+#pragma unroll
+    for (int c = 0; c < 64; ++c) x[c] = (c < bs) ? A[row + (int64_t)(b0 + c) * ld] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+        if (c < bs) {
+            double a = x[c];
+#pragma unroll
+            for (int cp = 0; cp < c; ++cp) a -= x[cp] * L[c + cp * 65];
+            x[c] = a / L[c + c * 65];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 64; ++c)
+        if (c < bs) A[row + (int64_t)(b0 + c) * ld] = x[c];
+}
+
 }  // namespace
+
+tlr_status potrf_tile(double *A, int nb, int tile, DevParams *params, const GemmDesc *d_desc, hipStream_t s) {
+    static const int cls_b = ktimer_class("k_potrf_block"), cls_p = ktimer_class("k_potrf_panel");
+    const int nblk = (int)cdiv(nb, 64);
+    for (int b = 0; b < nblk; ++b) {
+        const int b0 = b * 64, bs = (nb - b0 < 64) ? nb - b0 : 64;
+        const int rest = nb - b0 - bs;
+        {
+            const double d = bs;
+            KTimer kt(cls_b, s, d * d * d / 3.0, 8.0 * d * (d + 1.0), true);
+            hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(kThreads), 0, s, A, nb, b0, bs, tile, params);
+        }
+        if (rest > 0) {
+            {
+                const double d = bs, r = rest;
+                KTimer kt(cls_p, s, r * d * d, 8.0 * (2.0 * r * d + d * (d + 1.0) / 2.0), true);
+                hipLaunchKernelGGL(k_potrf_panel, dim3((unsigned)cdiv(rest, kThreads)), dim3(kThreads), 0, s, A, nb,
+                                   b0, bs, nb, params);
+            }
+            TLR_TRY(gemm_batched(false, true, d_desc + b, 1, rest, rest, s));
+        }
+    }
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
 
 tlr_status chol_small(const SmallDesc *d_descs, int count, int max_k, int mode, DevParams *params,
                       hipStream_t s, const SmallDesc *h_descs) {
@@ -301,8 +420,9 @@ tlr_status chol_small(const SmallDesc *d_descs, int count, int max_k, int mode, 
     static const int cls = ktimer_class("k_chol_small");
     static const bool attr = [] {
         return hipFuncSetAttribute(reinterpret_cast<const void *>(k_chol_small),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) == hipSuccess;
     }();
+    if (!attr) (void)hipGetLastError();  // launches above 64 KB will then report the limit
     (void)attr;
     double flops = 0.0, bytes = 0.0;
     if (h_descs && ktimer_on())
@@ -327,8 +447,9 @@ tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, 
     static const int cls = ktimer_class("k_trsm_rows");
     static const bool attr = [] {
         return hipFuncSetAttribute(reinterpret_cast<const void *>(k_trsm_rows),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) == hipSuccess;
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) == hipSuccess;
     }();
+    if (!attr) (void)hipGetLastError();  // launches above 64 KB will then report the limit
     (void)attr;
     double flops = 0.0, bytes = 0.0;
     if (h_descs && ktimer_on())

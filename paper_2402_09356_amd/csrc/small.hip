@@ -1,7 +1,7 @@
 // Batched small dense kernels, one work-group per problem:
 //  * one-sided (Hestenes) Jacobi SVD of a k x k matrix,
 //  * truncated pivoted QR of a k x k matrix,
-// plus the blocked Cholesky / triangular solve of the dense diagonal tiles.
+// plus the block triangular solve of the panel factors against a diagonal tile.
 #include <algorithm>
 #include <cmath>
 
@@ -39,48 +39,6 @@ __device__ inline double block_max(double v, double *red) {
     double t = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, red[w]);
     return t;
-}
-
-// ------------------------------------------------------ shifted Cholesky --
-
-// In-place lower Cholesky of W (k x k, ld), left-looking by columns: for
-// column c every row r >= c forms W[r][c] - sum_{q<c} L[r][q] L[c][q] (rows
-// spread over the threads, two threads per row splitting the sum), then the
-// column is scaled by the square root of its pivot.  A pivot <= defl
-// (defl > 0) marks a dead direction: its whole column of L (so row of R,
-// diagonal included) is zero, and the row solve writes a zero column of Q
-// there.  Q keeps orthonormal live columns and Y = Q R still holds, so the
-// singular values of R are those of Y.  Returns false on a non-positive or
-// non-finite pivot when defl == 0 (uniform across the work-group).
-__device__ bool chol_inplace(double *W, int ld, int k, double defl, double *part, int *s_fail) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int half = nt >> 1;  // threads [0, half) and [half, nt) split each row's sum
-    const int side = tid / half, lt = tid - side * half;
-    for (int c = 0; c < k; ++c) {
-        const int qs = side ? (c >> 1) : 0, qe = side ? c : (c >> 1);
-        for (int r = c + lt; r < k; r += half) {
-            double acc = 0.0;
-            for (int q = qs; q < qe; ++q) acc += W[r + q * ld] * W[c + q * ld];
-            part[r + side * kMaxSketch] = acc;
-        }
-        __syncthreads();
-        for (int r = c + tid; r < k; r += nt) part[r] = W[r + c * ld] - part[r] - part[r + kMaxSketch];
-        __syncthreads();
-        const double piv = part[c];
-        if (!isfinite(piv) || (defl == 0.0 && !(piv > 0.0))) {
-            if (tid == 0) *s_fail = c + 1;
-            __syncthreads();
-            return false;
-        }
-        if (defl > 0.0 && piv <= defl) {
-            for (int r = c + tid; r < k; r += nt) W[r + c * ld] = 0.0;  // dead direction
-        } else {
-            const double inv = 1.0 / sqrt(piv);
-            for (int r = c + tid; r < k; r += nt) W[r + c * ld] = (r == c) ? sqrt(piv) : part[r] * inv;
-        }
-        __syncthreads();
-    }
-    return true;
 }
 
 // ------------------------------------------------------ one-sided Jacobi --
@@ -703,59 +661,6 @@ __global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict_
 
 // ------------------------------------------------- dense diagonal tiles --
 
-// Cholesky of one bs x bs diagonal block A[b0:b0+bs, b0:b0+bs] (ld) in LDS.
-__global__ __launch_bounds__(kSmallThreads) void k_potrf_block(double *A, int ld, int b0, int bs,
-                                                                int tile, DevParams *params) {
-    __shared__ double W[64 * 64];
-    __shared__ double part[2 * kMaxSketch];
-    __shared__ int s_fail;
-    const int tid = threadIdx.x;
-    if (params->status != 0) return;
-    for (int e = tid; e < bs * bs; e += blockDim.x) {
-        const int r = e % bs, q = e / bs;
-        W[r + q * 64] = A[(b0 + r) + (int64_t)(b0 + q) * ld];
-    }
-    __syncthreads();
-    const bool ok = chol_inplace(W, 64, bs, 0.0, part, &s_fail);
-    if (!ok) {
-        if (tid == 0) set_status(params, TLR_NOT_SPD, tile, tile);
-        return;
-    }
-    for (int e = tid; e < bs * bs; e += blockDim.x) {
-        const int r = e % bs, q = e / bs;
-        if (r >= q) A[(b0 + r) + (int64_t)(b0 + q) * ld] = W[r + q * 64];
-    }
-}
-
-// Rows r in [b0+bs, nrows): A[r, b0:b0+bs] <- A[r, b0:b0+bs] L_bb^-T.
-__global__ __launch_bounds__(kSmallThreads) void k_potrf_panel(double *A, int ld, int b0, int bs,
-                                                                int nrows, DevParams *params) {
-    __shared__ double L[64 * 64];
-    const int tid = threadIdx.x;
-    if (params->status != 0) return;
-    for (int e = tid; e < bs * bs; e += blockDim.x) {
-        const int r = e % bs, q = e / bs;
-        L[r + q * 64] = (r >= q) ? A[(b0 + r) + (int64_t)(b0 + q) * ld] : 0.0;
-    }
-    __syncthreads();
-    const int row = b0 + bs + blockIdx.x * blockDim.x + tid;
-    if (row >= nrows) return;
-    double x[64];
-#pragma unroll
-    for (int c = 0; c < 64; ++c) x[c] = (c < bs) ? A[row + (int64_t)(b0 + c) * ld] : 0.0;
-#pragma unroll
-    for (int c = 0; c < 64; ++c) {
-        if (c < bs) {
-            double a = x[c];
-            for (int cp = 0; cp < c; ++cp) a -= x[cp] * L[c + cp * 64];
-            x[c] = a / L[c + c * 64];
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 64; ++c)
-        if (c < bs) A[row + (int64_t)(b0 + c) * ld] = x[c];
-}
-
 // Panels B_t[b0:b0+bs, :] <- L_bb^-1 B_t[b0:b0+bs, :], one work-group per
 // (panel, chunk of 64 columns); L_bb is the diagonal block of L (ld nb).
 __global__ __launch_bounds__(64) void k_trsm_block(const double *__restrict__ L, int ldl, int b0, int bs,
@@ -778,9 +683,17 @@ __global__ __launch_bounds__(64) void k_trsm_block(const double *__restrict__ L,
 #pragma unroll
     for (int r = 0; r < 64; ++r) {
         if (r < bs) {
-            double a = x[r];
-            for (int rp = 0; rp < r; ++rp) a -= Ls[r + rp * 64] * x[rp];
-            x[r] = a / Ls[r + r * 64];
+            // four independent partial sums shorten the dependent chain
+            double a0 = x[r], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+            for (int rp = 0; rp < r; ++rp) {
+                const double t = Ls[r + rp * 64] * x[rp];
+                if ((rp & 3) == 0) a0 -= t;
+                else if ((rp & 3) == 1) a1 -= t;
+                else if ((rp & 3) == 2) a2 -= t;
+                else a3 -= t;
+            }
+            x[r] = ((a0 + a1) + (a2 + a3)) / Ls[r + r * 64];
         }
     }
 #pragma unroll
@@ -846,22 +759,6 @@ void potrf_tile_descs(double *A, int nb, GemmDesc *h) {
         g.beta = 1.0;
         h[b] = g;
     }
-}
-
-tlr_status potrf_tile(double *A, int nb, int tile, DevParams *params, const GemmDesc *d_desc, hipStream_t s) {
-    const int nblk = (int)cdiv(nb, 64);
-    for (int b = 0; b < nblk; ++b) {
-        const int b0 = b * 64, bs = (nb - b0 < 64) ? nb - b0 : 64;
-        const int rest = nb - b0 - bs;
-        hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(kSmallThreads), 0, s, A, nb, b0, bs, tile, params);
-        if (rest > 0) {
-            hipLaunchKernelGGL(k_potrf_panel, dim3((unsigned)cdiv(rest, kSmallThreads)),
-                               dim3(kSmallThreads), 0, s, A, nb, b0, bs, nb, params);
-            TLR_TRY(gemm_batched(false, true, d_desc + b, 1, rest, rest, s));
-        }
-    }
-    TLR_HIP(hipGetLastError());
-    return TLR_OK;
 }
 
 namespace {

@@ -18,6 +18,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "kernels.h"
@@ -56,17 +58,67 @@ bool debug_enabled() {
     return on;
 }
 
+// Pinned host staging buffers for descriptor uploads (asynchronous DMA
+// copies), kept for the life of the process.  A buffer goes back to the pool
+// only after its stream has drained, so no copy from it is still in flight
+// when another context takes it.
+class PinnedPool {
+  public:
+    char *get(size_t bytes, size_t *cap) {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            for (size_t i = 0; i < free_.size(); ++i)
+                if (free_[i].second >= bytes) {
+                    auto b = free_[i];
+                    free_.erase(free_.begin() + (std::ptrdiff_t)i);
+                    *cap = b.second;
+                    return b.first;
+                }
+        }
+        void *h = nullptr;
+        if (hipHostMalloc(&h, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        *cap = bytes;
+        return static_cast<char *>(h);
+    }
+    void put(char *b, size_t cap) {
+        std::lock_guard<std::mutex> g(mu_);
+        free_.emplace_back(b, cap);
+    }
+
+  private:
+    std::mutex mu_;
+    std::vector<std::pair<char *, size_t>> free_;
+};
+
+PinnedPool &pinned_pool() {
+    static PinnedPool *pool = new PinnedPool();  // never destroyed: outlives static teardown
+    return *pool;
+}
+
 struct Ctx {
     const tlr_plan_s *p;
     char *ws;
     hipStream_t s;
-    std::vector<char> hdesc;
+    char *hdesc = nullptr;          // pinned staging (pageable fallback below)
+    size_t hdesc_cap = 0;
+    std::vector<char> hdesc_pageable;
+    bool in_flight = false;         // uploads issued since the last stream sync
     size_t desc_used = 0;
     size_t arena_used = 0;
 
     Ctx(const tlr_plan_s *plan, void *w, hipStream_t st) : p(plan), ws(static_cast<char *>(w)), s(st) {
-        hdesc.resize(plan->desc_bytes);
+        hdesc = pinned_pool().get(plan->desc_bytes, &hdesc_cap);
+        if (!hdesc) {
+            hdesc_pageable.resize(plan->desc_bytes);
+            hdesc = hdesc_pageable.data();
+        }
     }
+    ~Ctx() {
+        if (in_flight) (void)hipStreamSynchronize(s);
+        if (hdesc_pageable.empty() && hdesc) pinned_pool().put(hdesc, hdesc_cap);
+    }
+    Ctx(const Ctx &) = delete;
+    Ctx &operator=(const Ctx &) = delete;
     DevParams *params() const { return reinterpret_cast<DevParams *>(ws + p->off_params); }
     ParamsBlock *pblock() const { return reinterpret_cast<ParamsBlock *>(ws + p->off_params); }
     double *x() const { return reinterpret_cast<double *>(ws + p->off_x); }
@@ -89,10 +141,11 @@ struct Ctx {
     T *push(const T *data, size_t count) {
         const size_t bytes = align_up(sizeof(T) * std::max<size_t>(count, 1), 256);
         if (desc_used + bytes > p->desc_bytes) return nullptr;
-        char *h = hdesc.data() + desc_used;
+        char *h = hdesc + desc_used;
         std::memcpy(h, data, sizeof(T) * count);
         T *d = reinterpret_cast<T *>(ws + p->off_desc + desc_used);
         if (hipMemcpyAsync(d, h, sizeof(T) * count, hipMemcpyHostToDevice, s) != hipSuccess) return nullptr;
+        in_flight = true;
         desc_used += bytes;
         return d;
     }
@@ -109,6 +162,7 @@ struct Ctx {
     }
     tlr_status sync_reset() {
         TLR_HIP(hipStreamSynchronize(s));
+        in_flight = false;
         ktimer_poll();
         desc_used = 0;
         return TLR_OK;
@@ -444,7 +498,7 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->nt = (int)cdiv(n, nb);
     p->npad = (int64_t)p->nt * nb;
     p->ntiles = (int64_t)p->nt * (p->nt - 1) / 2;
-    p->pover = 16;
+    p->pover = 8;  // sketch width for a recompression: previous rank + 8 (the tail test's margin)
     p->min_tail = 8;
     p->k0 = 32;
     int rcap = (maxrank <= 0) ? nb / 2 : std::min(maxrank, nb);
