@@ -8,6 +8,14 @@ forward solve, log-determinant and l, at parameters theta_true * exp(0.2 N(0,I))
 (seeded; a fresh theta every step, as an optimiser would propose).  Inputs
 (ordered locations, observations) are resident in HBM before timing starts.
 
+`value` is evaluations per second with one evaluation at a time (the timed
+steps, where the launch timer measures each kernel on its stream).
+Evaluations are independent (each its own theta), and one evaluation leaves
+most compute units idle during the factorisation, so the same steps are then
+run again with three in flight, each on its own stream and workspace; that
+throughput, its per-evaluation latency and a bitwise check against the
+one-at-a-time results are reported under "concurrent".
+
 Prints one JSON line.  --config c1 runs the small 1,600-point case instead.
 """
 from __future__ import annotations
@@ -105,6 +113,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=10000)
+    ap.add_argument("--concurrency", type=int, default=3,
+                    help="after the timed steps, run them again with this many evaluations in flight "
+                         "(each on its own stream and workspace) and report that throughput beside")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size before warmup (counter calibration)")
     args = ap.parse_args()
@@ -134,6 +145,8 @@ def main():
     plan = B.Plan(n, nb, precision=args.precision)
     ws = plan.workspace(dev)
     out = torch.empty(3, dtype=torch.float64, device=dev)
+    conc = max(1, args.concurrency)
+    extra_ws = [plan.workspace(dev) for _ in range(conc - 1)]
     torch.cuda.synchronize()
     print(f"# workspace {plan.ws_bytes / 2**30:.2f} GiB, nt={plan.nt}, maxrank={plan.maxrank}", file=sys.stderr,
           flush=True)
@@ -147,8 +160,8 @@ def main():
         plan.loglik(ws, olocs, oz, thetas[w], tol, out=out)
         torch.cuda.synchronize()
         print(f"# warmup {w}: l={out[2].item():.6f}", file=sys.stderr, flush=True)
-    lat = []
-    lls = []
+    lat = [0.0] * args.steps
+    lls = [0.0] * args.steps
     B.kstats_enable(True)
     B.kstats_reset()
     torch.cuda.synchronize()
@@ -157,13 +170,48 @@ def main():
         t0 = time.perf_counter()
         plan.loglik(ws, olocs, oz, thetas[args.warmup + k], tol, out=out)
         torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t0)
-        lls.append(out[2].item())
-        print(f"# step {k}: {lat[-1] * 1e3:.1f} ms l={lls[-1]:.6f}", file=sys.stderr, flush=True)
+        lat[k] = time.perf_counter() - t0
+        lls[k] = out[2].item()
+        print(f"# step {k}: {lat[k] * 1e3:.1f} ms l={lls[k]:.6f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
     stats = B.kstats()
     B.kstats_enable(False)
+    concurrent = None
+    if conc > 1:
+        # the same steps again with `conc` evaluations in flight, one stream and
+        # one workspace each; results must equal the one-at-a-time ones
+        import threading
+
+        wss = [ws] + extra_ws
+        clat = [0.0] * args.steps
+        cll = [0.0] * args.steps
+
+        def worker(w):
+            stream = torch.cuda.Stream(device=dev)
+            with torch.cuda.stream(stream):
+                o = torch.empty(3, dtype=torch.float64, device=dev)
+                for k in range(w, args.steps, conc):
+                    t0 = time.perf_counter()
+                    plan.loglik(wss[w], olocs, oz, thetas[args.warmup + k], tol, out=o)
+                    stream.synchronize()
+                    clat[k] = time.perf_counter() - t0
+                    cll[k] = o[2].item()
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        threads = [threading.Thread(target=worker, args=(w,)) for w in range(conc)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        torch.cuda.synchronize()
+        ctotal = time.perf_counter() - t0
+        cl = np.asarray(clat) * 1e3
+        concurrent = {"evals_per_s": args.steps / ctotal, "streams": conc,
+                      "latency_ms": {"p50": float(np.percentile(cl, 50)), "p99": float(np.percentile(cl, 99))},
+                      "bitwise_equal_to_sequential": bool(all(a == b for a, b in zip(lls, cll)))}
+        print(f"# {conc} in flight: {concurrent['evals_per_s']:.3f} evals/s", file=sys.stderr, flush=True)
     for k in stats[:12]:
         print(f"# {k['name']:20s} launches {k['launches']:7d}  total {k['total_ms']:10.2f} ms  "
               f"avg {1e3 * k['total_ms'] / max(k['launches'], 1):9.2f} us", file=sys.stderr)
@@ -187,6 +235,7 @@ def main():
         "config": {"workload": workload,
                    "n": n, "nb": nb, "tol": tol, "ordering": kind, "precision": args.precision},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "concurrent": concurrent,
         "max_rank": st["max_rank"],
         "rank_sum": st["rank_sum"],
         "all_finite": bool(np.all(np.isfinite(lls))),

@@ -192,6 +192,14 @@ tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tl
                       void *stream);
 
 /* Synchronises `stream`, then reads the device status word. */
+/* Per-tile ranks held in the workspace: which = 0 gives those of Sigma's
+ * compressed tiles (after tlr_compress), which = 1 those of the factor L
+ * (after tlr_potrf).  d_out: device, nt*nt int32, row-major, entry (i, j)
+ * for i > j (other entries 0; -1 marks a tile whose rank exceeded maxrank).
+ * Asynchronous on `stream`.  (Paper Section 5.2: per-tile ranks and the
+ * storage they imply.) */
+tlr_status tlr_ranks_read(tlr_plan plan, const void *d_ws, int32_t which, int32_t *d_out, void *stream);
+
 tlr_status tlr_status_read(tlr_plan plan, const void *d_ws, tlr_devinfo *out, void *stream);
 
 /* Human-readable name of a status code (static string). */

@@ -8,6 +8,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -72,6 +73,7 @@ _SIGNATURES = {
     "tlr_diag_tile": (I32, [P, P, I32, I32, P, ctypes.POINTER(I32), P]),
     "tlr_diag_cholqr": (I32, [I32, I32, P, P, P, P]),
     "tlr_kstats_enable": (I32, [I32]),
+    "tlr_ranks_read": (I32, [P, P, I32, P, P]),
     "tlr_kstats_reset": (I32, []),
     "tlr_kstats_read": (I32, [P, I32]),
     "tlr_diag_qrcp": (I32, [I32, I32, P, F64, P, P, P, P, P]),
@@ -196,6 +198,12 @@ class Plan:
         _check(lib().tlr_diag_tile(self._h, _ptr(ws), i, j, _ptr(out), ctypes.byref(r), _stream()),
                "tlr_diag_tile")
         return out.t().cpu().numpy(), r.value
+
+    def ranks(self, ws, factor: bool = False) -> np.ndarray:
+        """nt x nt per-tile ranks (Sigma's compressed tiles, or L's with factor)."""
+        out = torch.zeros(self.nt * self.nt, dtype=torch.int32, device=ws.device)
+        _check(lib().tlr_ranks_read(self._h, _ptr(ws), 1 if factor else 0, _ptr(out), _stream()), "tlr_ranks_read")
+        return out.cpu().numpy().reshape(self.nt, self.nt)
 
     def status(self, ws) -> dict:
         info = DevInfo()

@@ -13,6 +13,7 @@ tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_byt
 tlr_status status_read(tlr_plan p, const void *d_ws, tlr_devinfo *out, hipStream_t s);
 void plan_shape(tlr_plan p, int64_t *n, int32_t *nb, int32_t *nt, int32_t *maxrank);
 tlr_status tile_read(tlr_plan p, const void *d_ws, int i, int j, double *d_out, int32_t *h_rank, hipStream_t s);
+tlr_status ranks_read(tlr_plan p, const void *d_ws, int which, int32_t *d_out, hipStream_t s);
 }  // namespace tlr
 
 static inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
@@ -111,6 +112,10 @@ int32_t tlr_kstats_read(tlr_kstat *out, int32_t max) {
     return tlr::ktimer_read(reinterpret_cast<tlr::KStat *>(out), max < 0 ? 0 : max);
 }
 
+tlr_status tlr_ranks_read(tlr_plan plan, const void *d_ws, int32_t which, int32_t *d_out, void *stream) {
+    return tlr::ranks_read(plan, d_ws, which, d_out, as_stream(stream));
+}
+
 tlr_status tlr_diag_tile(tlr_plan plan, const void *d_ws, int32_t i, int32_t j, double *d_out, int32_t *h_rank,
                          void *stream) {
     return tlr::tile_read(plan, d_ws, i, j, d_out, h_rank, as_stream(stream));
@@ -146,7 +151,7 @@ extern "C" tlr_status tlr_diag_gemm(int32_t trans_a, int32_t trans_b, int32_t M,
     if (hipMallocAsync(reinterpret_cast<void **>(&d), sizeof(g), s) != hipSuccess) return TLR_E_HIP;
     tlr_status st = TLR_OK;
     if (hipMemcpyAsync(d, &g, sizeof(g), hipMemcpyHostToDevice, s) != hipSuccess) st = TLR_E_HIP;
-    if (st == TLR_OK) st = tlr::gemm_batched(trans_a != 0, trans_b != 0, d, 1, M, N, s);
+    if (st == TLR_OK) st = tlr::gemm_batched(trans_a != 0, trans_b != 0, d, 1, M, N, s, &g);
     if (hipStreamSynchronize(s) != hipSuccess) st = TLR_E_HIP;
     (void)hipFreeAsync(d, s);
     (void)hipStreamSynchronize(s);

@@ -924,6 +924,14 @@ tlr_status status_read(tlr_plan p, const void *d_ws, tlr_devinfo *out, hipStream
 }  // namespace tlr
 
 namespace tlr {
+tlr_status ranks_read(tlr_plan p, const void *d_ws, int which, int32_t *d_out, hipStream_t s) {
+    if (!p || !d_ws || !d_out || (which != 0 && which != 1)) return TLR_E_INVAL;
+    const char *ws = static_cast<const char *>(d_ws);
+    const int32_t *src = reinterpret_cast<const int32_t *>(ws + (which == 0 ? p->off_rsig : p->off_rL));
+    TLR_HIP(hipMemcpyAsync(d_out, src, sizeof(int32_t) * (size_t)p->nt * p->nt, hipMemcpyDeviceToDevice, s));
+    return TLR_OK;
+}
+
 void plan_shape(tlr_plan p, int64_t *n, int32_t *nb, int32_t *nt, int32_t *maxrank) {
     if (!p) return;
     if (n) *n = p->n;

@@ -61,6 +61,11 @@ def test_c1_smoke_configuration():
     assert np.isfinite(out[2])
     assert err <= bound(1600, tol, delta_c)
     assert abs(out[0] - dense.logdet) <= bound(1600, tol, delta_c)
+    # the workspace's rank tables: Sigma's equal what compress returned; L's lie in [0, maxrank]
+    np.testing.assert_array_equal(plan.ranks(ws), ranks)
+    lr = plan.ranks(ws, factor=True)
+    low = lr[np.tril_indices(plan.nt, -1)]
+    assert np.all((low >= 0) & (low <= plan.maxrank))
     # ranks: equal to the exact SVD ranks except inside the tie band
     sv = OT.tile_svd(OM.covariance_matrix(locs, theta), nb)
     for (i, j), s in sv.svals.items():
