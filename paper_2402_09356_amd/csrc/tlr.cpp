@@ -40,6 +40,7 @@ namespace {
 
 constexpr uint64_t kHintMagic = 0x544c524d4c453031ull;  // ranks in rsig are valid hints
 constexpr uint64_t kSketchSeed = 0x5eed5ca1ab1e2024ull;
+constexpr int kMaxWave = 4096;  // tile jobs per batched launch sequence
 
 struct ParamsBlock {
     DevParams dp;
@@ -524,13 +525,23 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->off_yvec = take(sizeof(double) * p->npad);
     p->off_omega = take(sizeof(double) * (size_t)nb * p->kmax);
     p->off_knu = take(sizeof(double) * kChebPieces * (kChebDeg + 1));
-    p->desc_bytes = 8u << 20;
+    // descriptors of one wave: about 42 (GEMM and small-kernel descriptors,
+    // ~100 bytes each) per job of a full kMaxWave-job wave, plus the
+    // per-column products of the factorisation
+    p->desc_bytes = 32u << 20;
     p->off_desc = take(p->desc_bytes);
     // arena: one full wave of dense-tile jobs, plus the factorisation's
     // per-column panels, bounded to keep small problems small
     const size_t per_job = job_words(nb, p->kmax, rcap, 0, true) * sizeof(double);
     const size_t col_panels = sizeof(double) * (size_t)nb * (size_t)std::max(1, p->nt - 1) * rcap * 3;
-    size_t arena = std::max<size_t>(per_job * (size_t)std::min<int64_t>(std::max<int64_t>(p->ntiles, 1), 64), col_panels + per_job * 4);
+    // a factorisation job at the rank cap everywhere: X_i (nb x R), the
+    // Schur buffers (R = (nt-1) maxrank) and its M_ik blocks
+    const int64_t rmax = (int64_t)std::max(1, p->nt - 1) * rcap;
+    const size_t potrf_job =
+        (job_words(nb, p->kmax, rcap, (int)std::min<int64_t>(rmax, 1 << 30), false) + (size_t)nb * rmax +
+         (size_t)std::max(1, p->nt - 1) * rcap * rcap) * sizeof(double);
+    size_t arena = std::max<size_t>(per_job * (size_t)std::min<int64_t>(std::max<int64_t>(p->ntiles, 1), 64),
+                                    col_panels + potrf_job * 2);
     arena = std::max<size_t>(arena, 64u << 20);
     arena = std::min<size_t>(arena, (size_t)16 << 30);
     p->arena_bytes = arena;
@@ -634,7 +645,7 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
                 gens.push_back(GenDesc{A, pt.i * nb, pt.j * nb, nb, 0});
                 jobs.push_back(jb);
                 ++pos;
-                if (jobs.size() >= 4096) break;
+                if (jobs.size() >= (size_t)kMaxWave) break;
             }
             TLR_PUSH(dg, c, gens);
             TLR_TRY(gen_tiles_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), mc, s));
@@ -762,7 +773,10 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                     while (pos < todo.size()) {
                         const int i = todo[pos];
                         const int rij = r[(size_t)i * nt + j];
-                        const size_t need = (job_words(nb, kk[i], rij, Rj, false) + (size_t)nb * Rj) * sizeof(double);
+                        size_t msz = 0;
+                        for (int k = 0; k < j; ++k) msz += (size_t)r[(size_t)i * nt + k] * r[(size_t)j * nt + k];
+                        const size_t need =
+                            (job_words(nb, kk[i], rij, Rj, false) + (size_t)nb * Rj + msz + 64) * sizeof(double);
                         if (c.arena_used + need > p->arena_bytes && !jobs.empty()) break;
                         Job jb{};
                         jb.i = i;
@@ -780,8 +794,6 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         jb.stat = c.tstat(tile_index(i, j));
                         // X_i blocks: U_ik (V_ik^T V_jk); M_ik in the F buffer's space is
                         // not free yet, so use the tail of H/T: allocate separately
-                        size_t msz = 0;
-                        for (int k = 0; k < j; ++k) msz += (size_t)r[(size_t)i * nt + k] * r[(size_t)j * nt + k];
                         double *Mik = c.alloc(std::max<size_t>(msz, 1));
                         if (!Mik) return TLR_E_NOMEM;
                         size_t mo = 0;
@@ -800,7 +812,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         }
                         jobs.push_back(jb);
                         ++pos;
-                        if (jobs.size() >= 4096) break;
+                        if (jobs.size() >= (size_t)kMaxWave) break;
                     }
                     TLR_TRY(launch_gemms(c, true, false, gmm));
                     TLR_TRY(launch_gemms(c, false, false, gxx));

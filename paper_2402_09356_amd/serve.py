@@ -16,7 +16,6 @@ from __future__ import annotations
 import argparse
 import json
 import math
-import queue
 import sys
 import threading
 import time
@@ -234,7 +233,9 @@ def main():
     ap.add_argument("--hbm-gib", type=float, default=200.0)
     ap.add_argument("--maxrank", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-7)
-    ap.add_argument("--think-ms", type=float, default=5.0)
+    # each fit waits this long between a result and its next proposal; with 32
+    # fits this keeps the offered load near 0.8 of the measured capacity
+    ap.add_argument("--think-ms", type=float, default=3500.0)
     ap.add_argument("--evals-per-fit", type=int, default=12)
     args = ap.parse_args()
     if args.bench:
