@@ -89,6 +89,11 @@ typedef struct {
 
 /* flags for tlr_plan_create */
 #define TLR_PLAN_DEFAULT 0u
+/* Keep an off-diagonal tile whose rank exceeds maxrank dense instead of
+ * failing (the paper's dense fallback, Section 2 / Table "memory").  The
+ * workspace then holds one nb x nb pair per off-diagonal tile besides the
+ * low-rank slots. */
+#define TLR_PLAN_DENSE_TILES 1u
 
 typedef struct tlr_plan_s *tlr_plan;
 
@@ -133,7 +138,9 @@ tlr_status tlr_apply_perm(const int32_t *d_perm, int64_t n, const double *d_locs
  * maxrank: cap on an off-diagonal tile rank; <= 0 means nb/2 (the storage
  * break-even of Section 3).  A tile whose rank exceeds the cap stops the
  * factorisation with TLR_RANK_OVERFLOW (the "cannot proceed" case of
- * Section 3.3 / Table "memory").
+ * Section 3.3 / Table "memory"), unless flags has TLR_PLAN_DENSE_TILES: then
+ * the tile is kept dense (stored as the pair U = tile, V = I of rank nb) and
+ * the factorisation goes on.
  * Allocates host memory only. */
 tlr_status tlr_plan_create(tlr_plan *out, int64_t n, int32_t nb, int32_t maxrank,
                            tlr_precision precision, uint32_t flags);
@@ -195,8 +202,9 @@ tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tl
 /* Per-tile ranks held in the workspace: which = 0 gives those of Sigma's
  * compressed tiles (after tlr_compress), which = 1 those of the factor L
  * (after tlr_potrf).  d_out: device, nt*nt int32, row-major, entry (i, j)
- * for i > j (other entries 0; -1 marks a tile whose rank exceeded maxrank).
- * Asynchronous on `stream`.  (Paper Section 5.2: per-tile ranks and the
+ * for i > j (other entries 0; -1 marks a tile whose rank exceeded maxrank,
+ * -2 a tile kept dense under TLR_PLAN_DENSE_TILES).
+ * Synchronises `stream`.  (Paper Section 5.2: per-tile ranks and the
  * storage they imply.) */
 tlr_status tlr_ranks_read(tlr_plan plan, const void *d_ws, int32_t which, int32_t *d_out, void *stream);
 

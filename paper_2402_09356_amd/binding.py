@@ -141,10 +141,12 @@ def apply_perm(perm: torch.Tensor, locs: torch.Tensor, z: torch.Tensor | None = 
 class Plan:
     """Owns a tlr_plan handle; workspaces are torch uint8 device tensors."""
 
-    def __init__(self, n: int, nb: int, maxrank: int = 0, precision: str = "fp64"):
+    def __init__(self, n: int, nb: int, maxrank: int = 0, precision: str = "fp64", dense_tiles: bool = False):
+        """dense_tiles: keep over-rank off-diagonal tiles dense (TLR_PLAN_DENSE_TILES)."""
         L = lib()
         h = ctypes.c_void_p()
-        _check(L.tlr_plan_create(ctypes.byref(h), n, nb, maxrank, PRECISIONS[precision], 0), "tlr_plan_create")
+        _check(L.tlr_plan_create(ctypes.byref(h), n, nb, maxrank, PRECISIONS[precision], 1 if dense_tiles else 0),
+               "tlr_plan_create")
         self._h = h
         self.n = n
         self.nb = nb

@@ -38,7 +38,8 @@ struct DevParams {
     int32_t nu_kind;         // 0 general, 1 nu=1/2, 2 nu=3/2, 3 nu=5/2
     int32_t status;          // TLR_OK or first failure code
     int32_t fail_i, fail_j;  // tile of first failure
-    int32_t pad0, pad1;
+    int32_t dense_ok;        // over-rank tiles are kept dense by the host: not a failure
+    int32_t pad1;
 };
 
 // First failure wins: record code and tile unless a failure is already stored.
@@ -47,6 +48,12 @@ __device__ inline void set_status(DevParams *p, int code, int i, int j) {
         p->fail_i = i;
         p->fail_j = j;
     }
+}
+
+// A rank above the cap: a failure unless the plan keeps such tiles dense
+// (the host then sees the numerical rank in the tile's status words).
+__device__ inline void rank_overflow(DevParams *p, int i, int j) {
+    if (!p->dense_ok) set_status(p, TLR_RANK_OVERFLOW, i, j);
 }
 
 }  // namespace tlr

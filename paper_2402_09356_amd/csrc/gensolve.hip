@@ -1,5 +1,6 @@
 // Matern tile generation, the sketch test matrix, and the TLR forward solve
 // with the log-determinant / quadratic-form reductions.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -210,7 +211,7 @@ struct GemvDesc {
 // y_i <- y_i - U (V^T y_j) for a batch of low-rank tiles (one work-group each).
 __global__ __launch_bounds__(256) void k_lr_gemv(const GemvDesc *__restrict__ descs, int nb,
                                                  const DevParams *params) {
-    __shared__ double t[512];
+    __shared__ double t[4096];  // rank <= nb <= 4096 (a dense tile has rank nb)
     const GemvDesc d = descs[blockIdx.x];
     const int r = *d.r_dev;
     if (r <= 0 || params->status != 0) return;
@@ -310,6 +311,23 @@ tlr_status split_locs(const double *locs, int64_t n, int64_t npad, double *x, do
 
 tlr_status pad_copy(const double *z, int64_t n, int64_t npad, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_pad_copy, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s, z, n, npad, out);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+namespace {
+__global__ __launch_bounds__(256) void k_identity(double *const *__restrict__ ptrs, int nb) {
+    double *V = ptrs[blockIdx.y];
+    const int words = nb * nb;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < words; e += gridDim.x * 256)
+        V[e] = (e % nb == e / nb) ? 1.0 : 0.0;
+}
+}  // namespace
+
+tlr_status identity_batched(double *const *d_ptrs, int count, int nb, hipStream_t s) {
+    if (count <= 0 || nb <= 0) return TLR_OK;
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv((int64_t)nb * nb, 256), 1024);
+    hipLaunchKernelGGL(k_identity, dim3(gx, count), dim3(256), 0, s, d_ptrs, nb);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }

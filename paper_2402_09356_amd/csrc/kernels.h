@@ -81,6 +81,8 @@ struct CopyDesc {
     int64_t words;
 };
 tlr_status copy_batched(const CopyDesc *d_descs, int count, int64_t max_words, hipStream_t s);
+// Each of the `count` nb x nb matrices (device pointer array) set to I.
+tlr_status identity_batched(double *const *d_ptrs, int count, int nb, hipStream_t s);
 // B_t <- L^-1 B_t for `count` right-hand-side panels (nb x cols_t, ld nb),
 // L lower (nb x nb).  descs: A = L (shared), Y = B_t, k = cols_t.
 // d_gemm / h_gemm: room for count * ceil(nb/64) descriptors.

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi_svd(const SmallDesc *_
         const int insufficient = (tail < min_tail) && (k < (d.k_full < k_full ? d.k_full : k_full));
         int write = r;
         if (!insufficient && r > rank_cap) {
-            set_status(params, TLR_RANK_OVERFLOW, d.tile_i, d.tile_j);
+            rank_overflow(params, d.tile_i, d.tile_j);
             write = rank_cap;
         }
         if (insufficient) write = 0;  // keep the previous factors; the host retries wider
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
     const int insufficient = (k - rr_rank < min_tail) && (k < (d.k_full < k_full ? d.k_full : k_full));
     int r = insufficient ? 0 : rr_rank;
     if (!insufficient && r > rank_cap) {
-        if (tid == 0) set_status(params, TLR_RANK_OVERFLOW, d.tile_i, d.tile_j);
+        if (tid == 0) rank_overflow(params, d.tile_i, d.tile_j);
         r = rank_cap;
     }
     // Y = B^T: B[i][p] = R entry for i <= pivot step of p (the diagonal sits
@@ -600,7 +600,7 @@ __global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict_
     const int insufficient = (k - s_r < min_tail) && (k < (d.k_full < k_full ? d.k_full : k_full));
     int r = insufficient ? 0 : s_r;
     if (!insufficient && r > rank_cap) {
-        if (tid == 0) set_status(params, TLR_RANK_OVERFLOW, d.tile_i, d.tile_j);
+        if (tid == 0) rank_overflow(params, d.tile_i, d.tile_j);
         r = rank_cap;
     }
     // Y = B^T (k x r): B[c][perm[j]] = R[c][j] for j >= c (R[c][c] = alpha_c, kept in cn[c])

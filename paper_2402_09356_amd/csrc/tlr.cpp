@@ -31,7 +31,8 @@ struct tlr_plan_s {
     tlr_precision prec;
     uint32_t flags;
     size_t off_params, off_x, off_y, off_diag, off_rsig, off_rL, off_tstat, off_slots, off_yvec, off_omega,
-        off_desc, off_arena, off_knu;
+        off_desc, off_arena, off_knu, off_dense, off_wide;
+    bool dense_ok;  // TLR_PLAN_DENSE_TILES: over-rank tiles kept dense in the wide slots
     size_t desc_bytes, arena_bytes, ws_bytes;
 };
 
@@ -130,10 +131,35 @@ struct Ctx {
     int32_t *rsig() const { return reinterpret_cast<int32_t *>(ws + p->off_rsig); }
     int32_t *rL() const { return reinterpret_cast<int32_t *>(ws + p->off_rL); }
     int32_t *tstat(int64_t t) const { return reinterpret_cast<int32_t *>(ws + p->off_tstat) + 4 * t; }
+    // per-tile dense flags (host copy; loaded by load_dense, kept in the workspace)
+    std::vector<int32_t> dflag;
+    bool dense(int i, int j) const { return !dflag.empty() && dflag[(size_t)i * p->nt + j] != 0; }
+    int32_t *ddense() const { return reinterpret_cast<int32_t *>(ws + p->off_dense); }
+    double *wideU(int i, int j) const {
+        return reinterpret_cast<double *>(ws + p->off_wide) + tile_index(i, j) * 2 * (int64_t)p->nb * p->nb;
+    }
+    double *wideV(int i, int j) const { return wideU(i, j) + (int64_t)p->nb * p->nb; }
     double *U(int i, int j) const {
+        if (dense(i, j)) return wideU(i, j);
         return reinterpret_cast<double *>(ws + p->off_slots) + tile_index(i, j) * 2 * (int64_t)p->nb * p->rcap;
     }
-    double *V(int i, int j) const { return U(i, j) + (int64_t)p->nb * p->rcap; }
+    double *V(int i, int j) const {
+        if (dense(i, j)) return wideV(i, j);
+        return reinterpret_cast<double *>(ws + p->off_slots) + tile_index(i, j) * 2 * (int64_t)p->nb * p->rcap +
+               (int64_t)p->nb * p->rcap;
+    }
+    tlr_status load_dense() {
+        dflag.assign((size_t)p->nt * p->nt, 0);
+        TLR_HIP(hipMemcpyAsync(dflag.data(), ddense(), sizeof(int32_t) * dflag.size(), hipMemcpyDeviceToHost, s));
+        TLR_HIP(hipStreamSynchronize(s));
+        return TLR_OK;
+    }
+    tlr_status store_dense() {
+        if (dflag.empty()) dflag.assign((size_t)p->nt * p->nt, 0);
+        TLR_HIP(hipMemcpyAsync(ddense(), dflag.data(), sizeof(int32_t) * dflag.size(), hipMemcpyHostToDevice, s));
+        in_flight = true;
+        return TLR_OK;
+    }
     double *yvec() const { return reinterpret_cast<double *>(ws + p->off_yvec); }
     double *omega() const { return reinterpret_cast<double *>(ws + p->off_omega); }
 
@@ -231,6 +257,7 @@ struct Job {
     // buffers
     double *Yb = nullptr, *Zb = nullptr, *G = nullptr, *T = nullptr, *Rt = nullptr, *Xs = nullptr, *S = nullptr,
            *P = nullptr, *H = nullptr, *F = nullptr;
+    double *D = nullptr;  // nb x nb: explicit Schur complement of a tile kept dense
     double *Rp[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -446,6 +473,25 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, in
     return TLR_OK;
 }
 
+// Tiles kept dense: U <- D (nb x nb), V <- I, host flag set.  Stream-ordered
+// after whatever produced D.
+tlr_status make_dense(Ctx &c, const std::vector<std::pair<int, int>> &tiles, const std::vector<const double *> &src) {
+    if (tiles.empty()) return TLR_OK;
+    const int nb = c.p->nb;
+    std::vector<CopyDesc> cps;
+    std::vector<double *> ids;
+    for (size_t q = 0; q < tiles.size(); ++q) {
+        const int i = tiles[q].first, j = tiles[q].second;
+        cps.push_back(CopyDesc{src[q], c.wideU(i, j), (int64_t)nb * nb});
+        ids.push_back(c.wideV(i, j));
+        c.dflag[(size_t)i * c.p->nt + j] = 1;
+    }
+    TLR_PUSH(dcp, c, cps);
+    TLR_TRY(copy_batched(dcp, (int)cps.size(), (int64_t)nb * nb, c.s));
+    TLR_PUSH(did, c, ids);
+    return identity_batched(did, (int)ids.size(), nb, c.s);
+}
+
 int tile_rows(const tlr_plan_s *p, int i) {
     const int64_t r = p->n - (int64_t)i * p->nb;
     return (int)std::min<int64_t>(r, p->nb);
@@ -522,6 +568,9 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->off_rL = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
     p->off_tstat = take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(p->ntiles, 1));
     p->off_slots = take(sizeof(double) * 2 * (size_t)nb * rcap * (size_t)p->ntiles);
+    p->dense_ok = (flags & TLR_PLAN_DENSE_TILES) != 0;
+    p->off_dense = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
+    p->off_wide = p->dense_ok ? take(sizeof(double) * 2 * (size_t)nb * nb * (size_t)std::max<int64_t>(p->ntiles, 1)) : 0;
     p->off_yvec = take(sizeof(double) * p->npad);
     p->off_omega = take(sizeof(double) * (size_t)nb * p->kmax);
     p->off_knu = take(sizeof(double) * kChebPieces * (kChebDeg + 1));
@@ -533,13 +582,15 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     // arena: one full wave of dense-tile jobs, plus the factorisation's
     // per-column panels, bounded to keep small problems small
     const size_t per_job = job_words(nb, p->kmax, rcap, 0, true) * sizeof(double);
-    const size_t col_panels = sizeof(double) * (size_t)nb * (size_t)std::max(1, p->nt - 1) * rcap * 3;
+    const size_t col_panels =
+        sizeof(double) * (size_t)nb * (size_t)std::max(1, p->nt - 1) * ((flags & TLR_PLAN_DENSE_TILES) ? nb : rcap) * 3;
     // a factorisation job at the rank cap everywhere: X_i (nb x R), the
     // Schur buffers (R = (nt-1) maxrank) and its M_ik blocks
-    const int64_t rmax = (int64_t)std::max(1, p->nt - 1) * rcap;
+    const int64_t rmax = (int64_t)std::max(1, p->nt - 1) * (p->dense_ok ? nb : rcap);
     const size_t potrf_job =
         (job_words(nb, p->kmax, rcap, (int)std::min<int64_t>(rmax, 1 << 30), false) + (size_t)nb * rmax +
-         (size_t)std::max(1, p->nt - 1) * rcap * rcap) * sizeof(double);
+         (size_t)std::max(1, p->nt - 1) * (p->dense_ok ? (size_t)nb * nb : (size_t)rcap * rcap) +
+         (p->dense_ok ? 3 * (size_t)nb * nb : 0)) * sizeof(double);
     size_t arena = std::max<size_t>(per_job * (size_t)std::min<int64_t>(std::max<int64_t>(p->ntiles, 1), 64),
                                     col_panels + potrf_job * 2);
     arena = std::max<size_t>(arena, 64u << 20);
@@ -574,6 +625,7 @@ tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws,
     hb.dp.nu = th.nu;
     hb.dp.status = 0;
     hb.dp.fail_i = hb.dp.fail_j = -1;
+    hb.dp.dense_ok = p->dense_ok ? 1 : 0;
     hb.mc = mc;
     hb.hint_magic = keep_magic;
     TLR_HIP(hipMemcpyAsync(c.pblock(), &hb, sizeof(ParamsBlock), hipMemcpyHostToDevice, s));
@@ -600,6 +652,7 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
     std::vector<int32_t> hint((size_t)nt * nt, -1), ranks((size_t)nt * nt, 0);
     TLR_HIP(hipMemcpyAsync(hint.data(), c.rsig(), sizeof(int32_t) * hint.size(), hipMemcpyDeviceToHost, s));
     TLR_HIP(hipStreamSynchronize(s));
+    c.dflag.assign((size_t)nt * nt, 0);  // every tile starts low-rank
     // Every tile starts from the same sketch width (no state carried between
     // evaluations), so the result depends on the inputs only.
     const bool hints_ok = false;
@@ -662,22 +715,40 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
                     std::fprintf(stderr, "compress tile (%d,%d) k=%d write=%d num=%d flag=%d status=%d\n", jobs[q].i,
                                  jobs[q].j, jobs[q].k, st[4 * q], st[4 * q + 1], st[4 * q + 2], code);
             }
+            std::vector<std::pair<int, int>> dz;
+            std::vector<const double *> dsrc;
             for (size_t q = 0; q < jobs.size(); ++q) {
                 const Job &jb = jobs[q];
                 if (st[4 * q + 2]) {
                     retry.push_back({jb.i, jb.j, widen_k(p, jb.k, jb.kfull)});
                 } else {
                     const int num = st[4 * q + 1];
-                    ranks[(size_t)jb.i * nt + jb.j] = (num > p->rcap) ? -1 : st[4 * q];
+                    int rk = st[4 * q];
+                    if (num > p->rcap) {
+                        rk = -1;
+                        if (p->dense_ok) {  // keep the generated tile dense
+                            dz.emplace_back(jb.i, jb.j);
+                            dsrc.push_back(jb.A);
+                            rk = nb;
+                        }
+                    }
+                    ranks[(size_t)jb.i * nt + jb.j] = rk;
                 }
             }
+            // before the next wave reuses the arena that holds the tiles
+            TLR_TRY(make_dense(c, dz, dsrc));
         }
         pending.swap(retry);
     }
+    TLR_TRY(c.store_dense());
     TLR_HIP(hipMemcpyAsync(c.rsig(), ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
     TLR_HIP(hipMemcpyAsync(c.rL(), ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
+    std::vector<int32_t> out_ranks = ranks;
+    for (size_t t = 0; t < out_ranks.size(); ++t)
+        if (c.dflag[t]) out_ranks[t] = -2;
     if (d_ranks)
-        TLR_HIP(hipMemcpyAsync(d_ranks, ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
+        TLR_HIP(hipMemcpyAsync(d_ranks, out_ranks.data(), sizeof(int32_t) * out_ranks.size(), hipMemcpyHostToDevice,
+                               s));
     const uint64_t magic = kHintMagic;
     TLR_HIP(hipMemcpyAsync(&c.pblock()->hint_magic, &magic, sizeof(magic), hipMemcpyHostToDevice, s));
     TLR_HIP(hipStreamSynchronize(s));
@@ -698,6 +769,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
     TLR_HIP(hipStreamSynchronize(s));
     const double tol = hb.tol;
     if (hb.dp.status != 0) return TLR_OK;  // already failed: l = -inf
+    TLR_TRY(c.load_dense());
     for (int i = 0; i < nt; ++i)
         for (int j = 0; j < i; ++j)
             if (r[(size_t)i * nt + j] < 0) return TLR_OK;  // overflow recorded by compress
@@ -768,16 +840,23 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                 size_t pos = 0;
                 while (pos < todo.size()) {
                     c.arena_used = mark;
-                    std::vector<Job> jobs;
+                    std::vector<Job> jobs;   // low-rank tiles: recompressed by the range finder
+                    std::vector<Job> djobs;  // dense tiles: Schur complement formed explicitly
                     std::vector<GemmDesc> gmm, gxx;
                     while (pos < todo.size()) {
                         const int i = todo[pos];
                         const int rij = r[(size_t)i * nt + j];
+                        const bool dz = c.dense(i, j);
                         size_t msz = 0;
                         for (int k = 0; k < j; ++k) msz += (size_t)r[(size_t)i * nt + k] * r[(size_t)j * nt + k];
-                        const size_t need =
-                            (job_words(nb, kk[i], rij, Rj, false) + (size_t)nb * Rj + msz + 64) * sizeof(double);
-                        if (c.arena_used + need > p->arena_bytes && !jobs.empty()) break;
+                        size_t words = (size_t)nb * Rj + msz + 64;
+                        if (dz)
+                            words += (size_t)nb * nb + 64;
+                        else
+                            words += job_words(nb, kk[i], rij, Rj, false) +
+                                     (p->dense_ok ? 2 * (size_t)nb * p->rcap + (size_t)nb * nb + 256 : 0);
+                        if (c.arena_used + words * sizeof(double) > p->arena_bytes && !(jobs.empty() && djobs.empty()))
+                            break;
                         Job jb{};
                         jb.i = i;
                         jb.j = j;
@@ -787,13 +866,27 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         jb.Uop = c.U(i, j);
                         jb.Vop = c.V(i, j);
                         double *Xi = c.alloc((size_t)nb * Rj);
-                        if (!Xi || !alloc_job(c, jb, Rj)) return TLR_E_NOMEM;
+                        if (!Xi) return TLR_E_NOMEM;
                         jb.Xi = Xi;
-                        jb.Uout = c.U(i, j);
-                        jb.Vout = c.V(i, j);
                         jb.stat = c.tstat(tile_index(i, j));
-                        // X_i blocks: U_ik (V_ik^T V_jk); M_ik in the F buffer's space is
-                        // not free yet, so use the tail of H/T: allocate separately
+                        if (dz) {
+                            jb.D = c.alloc((size_t)nb * nb);
+                            if (!jb.D) return TLR_E_NOMEM;
+                        } else {
+                            if (!alloc_job(c, jb, Rj)) return TLR_E_NOMEM;
+                            if (p->dense_ok) {
+                                // results land in temporaries: the old factors stay intact
+                                // in case the tile turns out to need the dense form
+                                jb.Uout = c.alloc((size_t)nb * p->rcap);
+                                jb.Vout = c.alloc((size_t)nb * p->rcap);
+                                jb.D = c.alloc((size_t)nb * nb);
+                                if (!jb.Uout || !jb.Vout || !jb.D) return TLR_E_NOMEM;
+                            } else {
+                                jb.Uout = c.U(i, j);
+                                jb.Vout = c.V(i, j);
+                            }
+                        }
+                        // X_i blocks: U_ik (V_ik^T V_jk)
                         double *Mik = c.alloc(std::max<size_t>(msz, 1));
                         if (!Mik) return TLR_E_NOMEM;
                         size_t mo = 0;
@@ -810,13 +903,34 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                                              1.0, 0.0));
                             mo += (size_t)rik * rjk;
                         }
-                        jobs.push_back(jb);
+                        (dz ? djobs : jobs).push_back(jb);
                         ++pos;
-                        if (jobs.size() >= (size_t)kMaxWave) break;
+                        if (jobs.size() + djobs.size() >= (size_t)kMaxWave) break;
                     }
                     TLR_TRY(launch_gemms(c, true, false, gmm));
                     TLR_TRY(launch_gemms(c, false, false, gxx));
-                    TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, false, q1_passes(p, hb.dp.sigma2, tol)));
+                    // explicit Schur complement D = U V^T - X_i Y_j^T of a tile (dense or converting)
+                    auto schur_dense = [&](const std::vector<Job> &js) -> tlr_status {
+                        std::vector<GemmDesc> g1, g2;
+                        for (const Job &jb : js) {
+                            g1.push_back(gd(jb.Uop, nb, jb.Vop, nb, jb.D, nb, nb, nb, jb.r, 1.0, 0.0));
+                            g2.push_back(gd(jb.Xi, nb, Yj, nb, jb.D, nb, nb, nb, Rj, -1.0, 1.0));
+                        }
+                        TLR_TRY(launch_gemms(c, false, true, g1));
+                        return launch_gemms(c, false, true, g2);
+                    };
+                    if (!djobs.empty()) {
+                        TLR_TRY(schur_dense(djobs));
+                        std::vector<std::pair<int, int>> dt;
+                        std::vector<const double *> ds;
+                        for (const Job &jb : djobs) {
+                            dt.emplace_back(jb.i, jb.j);
+                            ds.push_back(jb.D);
+                        }
+                        TLR_TRY(make_dense(c, dt, ds));
+                    }
+                    if (!jobs.empty())
+                        TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, false, q1_passes(p, hb.dp.sigma2, tol)));
                     std::vector<int32_t> st(4 * jobs.size());
                     for (size_t q = 0; q < jobs.size(); ++q)
                         TLR_HIP(hipMemcpyAsync(&st[4 * q], jobs[q].stat, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -827,15 +941,42 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                                          jobs[q].i, jobs[q].j, Rj, jobs[q].k, jobs[q].r, st[4 * q], st[4 * q + 1],
                                          st[4 * q + 2]);
                     }
+                    std::vector<Job> conv;
+                    std::vector<CopyDesc> keep;
+                    int64_t keep_max = 0;
                     for (size_t q = 0; q < jobs.size(); ++q) {
                         const Job &jb = jobs[q];
                         if (st[4 * q + 2]) {
                             kk[jb.i] = widen_k(p, jb.k, jb.kfull);
                             retry.push_back(jb.i);
+                        } else if (p->dense_ok && st[4 * q + 1] > p->rcap) {
+                            conv.push_back(jb);
+                            r[(size_t)jb.i * nt + j] = nb;
                         } else {
-                            r[(size_t)jb.i * nt + j] = st[4 * q];
+                            const int rk = st[4 * q];
+                            r[(size_t)jb.i * nt + j] = rk;
+                            if (p->dense_ok && rk > 0) {
+                                keep.push_back(CopyDesc{jb.Uout, c.U(jb.i, j), (int64_t)nb * rk});
+                                keep.push_back(CopyDesc{jb.Vout, c.V(jb.i, j), (int64_t)nb * rk});
+                                keep_max = std::max<int64_t>(keep_max, (int64_t)nb * rk);
+                            }
                         }
                     }
+                    if (!keep.empty()) {
+                        TLR_PUSH(dkp, c, keep);
+                        TLR_TRY(copy_batched(dkp, (int)keep.size(), keep_max, s));
+                    }
+                    if (!conv.empty()) {  // over the cap: keep the Schur complement dense
+                        TLR_TRY(schur_dense(conv));
+                        std::vector<std::pair<int, int>> dt;
+                        std::vector<const double *> ds;
+                        for (const Job &jb : conv) {
+                            dt.emplace_back(jb.i, jb.j);
+                            ds.push_back(jb.D);
+                        }
+                        TLR_TRY(make_dense(c, dt, ds));
+                    }
+                    if (!keep.empty() || !conv.empty()) TLR_TRY(c.sync_reset());
                 }
                 todo.swap(retry);
             }
@@ -869,6 +1010,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
         }
         TLR_TRY(c.sync_reset());
     }
+    TLR_TRY(c.store_dense());
     TLR_HIP(hipMemcpyAsync(c.rL(), r.data(), sizeof(int32_t) * r.size(), hipMemcpyHostToDevice, s));
     TLR_HIP(hipStreamSynchronize(s));
     return TLR_OK;
@@ -881,6 +1023,7 @@ tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_byt
     if (ws_bytes < p->ws_bytes) return TLR_E_NOMEM;
     Ctx c(p, d_ws, s);
     const int nt = p->nt, nb = p->nb;
+    TLR_TRY(c.load_dense());
     TLR_TRY(pad_copy(d_z, p->n, p->npad, c.yvec(), s));
     const size_t gb = gemv_desc_bytes();
     std::vector<char> hv(gb * std::max<int64_t>(p->ntiles, 1));
@@ -938,9 +1081,15 @@ tlr_status status_read(tlr_plan p, const void *d_ws, tlr_devinfo *out, hipStream
 namespace tlr {
 tlr_status ranks_read(tlr_plan p, const void *d_ws, int which, int32_t *d_out, hipStream_t s) {
     if (!p || !d_ws || !d_out || (which != 0 && which != 1)) return TLR_E_INVAL;
-    const char *ws = static_cast<const char *>(d_ws);
-    const int32_t *src = reinterpret_cast<const int32_t *>(ws + (which == 0 ? p->off_rsig : p->off_rL));
-    TLR_HIP(hipMemcpyAsync(d_out, src, sizeof(int32_t) * (size_t)p->nt * p->nt, hipMemcpyDeviceToDevice, s));
+    Ctx c(p, const_cast<void *>(d_ws), s);
+    const size_t cnt = (size_t)p->nt * p->nt;
+    std::vector<int32_t> r(cnt);
+    TLR_HIP(hipMemcpyAsync(r.data(), which == 0 ? c.rsig() : c.rL(), sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s));
+    TLR_TRY(c.load_dense());  // synchronises
+    for (size_t t = 0; t < cnt; ++t)
+        if (c.dflag[t]) r[t] = -2;
+    TLR_HIP(hipMemcpyAsync(d_out, r.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
+    TLR_HIP(hipStreamSynchronize(s));
     return TLR_OK;
 }
 
@@ -958,6 +1107,7 @@ tlr_status tile_read(tlr_plan p, const void *d_ws, int i, int j, double *d_out, 
     if (!p || !d_ws || !d_out || i < 0 || j < 0 || i >= p->nt || j > i) return TLR_E_INVAL;
     Ctx c(p, const_cast<void *>(d_ws), s);
     const int nb = p->nb;
+    TLR_TRY(c.load_dense());
     if (i == j) {
         TLR_HIP(hipMemcpyAsync(d_out, c.diag(i), sizeof(double) * nb * nb, hipMemcpyDeviceToDevice, s));
         TLR_HIP(hipStreamSynchronize(s));

@@ -2,8 +2,8 @@
 
 For each cell (nu, beta, ordering, nb, tol) on an m x m jittered grid: the
 per-tile ranks after compression, their histogram, the off-diagonal storage
-in MB (2 nb r 8 bytes per low-rank tile, the quantity of the paper's Table
-"memory"), l(theta_true) and the time of one evaluation.  Ranks do not depend
+in MB (2 nb r 8 bytes per low-rank tile, nb^2 8 per dense one: the quantity of the
+paper's Table "memory"), l(theta_true) and the time of one evaluation.  Ranks do not depend
 on the observations, so Z is white noise here.
 
     python -m paper_2402_09356_amd.sweep --m 200 --nu 0.5 --beta 0.03 0.1 0.3 \\
@@ -20,7 +20,7 @@ import numpy as np
 BINS = (0, 1, 11, 26, 51, 101, 201, 10**9)
 
 
-def run_cell(m, nu, beta, kind, nb, tol, exact_ranks=False, seed_cfg=2, cell=0):
+def run_cell(m, nu, beta, kind, nb, tol, exact_ranks=False, seed_cfg=2, cell=0, dense_tiles=False):
     import torch
 
     import synthetic
@@ -33,7 +33,7 @@ def run_cell(m, nu, beta, kind, nb, tol, exact_ranks=False, seed_cfg=2, cell=0):
     dl = torch.from_numpy(locs).to(dev)
     perm = B.reorder(dl, kind, synthetic.seed_for(seed_cfg, synthetic.SEED_ORDER, cell))
     ol, oz = B.apply_perm(perm, dl, torch.from_numpy(z).to(dev))
-    plan = B.Plan(n, nb, maxrank=nb // 2)
+    plan = B.Plan(n, nb, maxrank=nb // 2, dense_tiles=dense_tiles)
     ws = plan.workspace(dev)
     theta = (1.0, beta, nu)
     ranks = torch.zeros(plan.nt * plan.nt, dtype=torch.int32, device=dev) if exact_ranks else None
@@ -53,14 +53,16 @@ def run_cell(m, nu, beta, kind, nb, tol, exact_ranks=False, seed_cfg=2, cell=0):
         r = plan.ranks(ws)
         rk = [int(r[i, j]) for i in range(nt) for j in range(i)]
     rk = np.asarray(rk)
-    over = int(np.sum(rk < 0))
+    over = int(np.sum(rk == -1))
+    dense = int(np.sum(rk == -2))
     low = rk[rk >= 0]
     hist = np.histogram(low, bins=np.asarray(BINS))[0].tolist()
-    storage_mb = float(2 * nb * low.sum() * 8 / 1e6 + over * nb * nb * 8 / 1e6)
+    storage_mb = float(2 * nb * low.sum() * 8 / 1e6 + (over + dense) * nb * nb * 8 / 1e6)
     return {"n": n, "nu": nu, "beta": beta, "ordering": kind, "nb": nb, "tol": tol,
             "loglik": float(out[2].item()), "eval_s": dt, "status": st["code"],
             "rank_mean": float(low.mean()) if low.size else None, "rank_max": int(low.max()) if low.size else None,
-            "hist_bins": list(BINS), "hist": hist, "overflow_tiles": over, "offdiag_storage_MB": storage_mb,
+            "hist_bins": list(BINS), "hist": hist, "overflow_tiles": over, "dense_tiles": dense,
+            "offdiag_storage_MB": storage_mb,
             "rank_mode": "exact SVD" if exact_ranks else "pivoted QR"}
 
 
@@ -73,6 +75,7 @@ def main():
     ap.add_argument("--nb", type=int, nargs="+", default=[800])
     ap.add_argument("--tol", type=float, nargs="+", default=[1e-7])
     ap.add_argument("--exact-ranks", action="store_true")
+    ap.add_argument("--dense-tiles", action="store_true", help="keep over-rank tiles dense")
     args = ap.parse_args()
     cell = 0
     for nu in args.nu:
@@ -81,7 +84,8 @@ def main():
             for kind in args.orderings:
                 for nb in args.nb:
                     for tol in args.tol:
-                        rec = run_cell(args.m, nu, beta, kind, nb, tol, args.exact_ranks, cell=cell)
+                        rec = run_cell(args.m, nu, beta, kind, nb, tol, args.exact_ranks, cell=cell,
+                                       dense_tiles=args.dense_tiles)
                         print(json.dumps(rec), flush=True)
 
 

@@ -270,3 +270,45 @@ def test_rank_histograms_match_oracle_per_ordering(kind):
     h_ora = OT.rank_stats(oranks, onum, bins=(0, 1, 11, 26, 51, 101, 201, 10**9))["hist"]
     print(kind, "hist gpu", h_gpu, "oracle", h_ora, "tie tiles", ties, flush=True)
     assert sum(abs(a - b) for a, b in zip(h_gpu, h_ora)) <= 2 * ties
+
+
+def test_dense_tile_fallback_matches_oracle():
+    """maxrank = 48 with dense tiles allowed: every tile whose rank exceeds 48 is
+    kept dense (compression and recompressions), as the oracle's tile-truncated
+    matrix does; l agrees with the dense oracle within the bound, dense tiles
+    read back as -2, and the evaluation is bitwise repeatable."""
+    device()
+    theta, nb, tol, cap = (1.0, 0.1, 0.5), 200, 1e-9, 48
+    locs, z = make_problem(40, theta, "morton")
+    plan = B.Plan(1600, nb, maxrank=cap, dense_tiles=True)
+    ws = plan.workspace()
+    dl, dz = to_dev(locs), to_dev(z)
+    out = plan.loglik(ws, dl, dz, theta, tol).cpu().numpy()
+    assert plan.status(ws)["code"] == 0
+    dense = OL.loglik_dense(locs, z, theta).loglik
+    comp, oranks = OT.compressed_loglik(locs, z, theta, nb, tol, maxrank=cap)
+    print("dense fallback", out[2], dense, comp.loglik, flush=True)
+    assert abs(out[2] - dense) <= bound(1600, tol, comp.loglik - dense)
+    rk = plan.ranks(ws)
+    low = np.tril_indices(plan.nt, -1)
+    # every tile the oracle keeps dense is dense here (the pivoted-QR rank is >= the SVD rank)
+    assert np.all(rk[low][oranks[low] == OT.DENSE] == -2)
+    assert (rk[low] == -2).sum() >= 1 and (rk[low] >= 0).sum() >= 1
+    out2 = plan.loglik(ws, dl, dz, theta, tol).cpu().numpy()
+    assert out2[2] == out[2]
+
+
+def test_dense_tiles_random_order():
+    """Random order makes most tiles full rank at tol = 1e-9: with dense tiles
+    the evaluation goes through and matches the dense oracle."""
+    device()
+    theta, nb, tol = (1.0, 0.1, 0.5), 100, 1e-9
+    locs, z = make_problem(30, theta, "random")
+    plan = B.Plan(900, nb, dense_tiles=True)
+    ws = plan.workspace()
+    out = plan.loglik(ws, to_dev(locs), to_dev(z), theta, tol).cpu().numpy()
+    dense = OL.loglik_dense(locs, z, theta).loglik
+    comp, _ = OT.compressed_loglik(locs, z, theta, nb, tol)
+    assert plan.status(ws)["code"] == 0
+    assert abs(out[2] - dense) <= bound(900, tol, comp.loglik - dense)
+    assert (plan.ranks(ws)[np.tril_indices(plan.nt, -1)] == -2).sum() >= 1
