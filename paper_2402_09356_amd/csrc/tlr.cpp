@@ -15,6 +15,7 @@
 //   desc      kernel descriptor staging area
 //   arena     per-wave scratch (dense tiles, sketches, small matrices)
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -106,6 +107,7 @@ struct Ctx {
     std::vector<char> hdesc_pageable;
     bool in_flight = false;         // uploads issued since the last stream sync
     size_t desc_used = 0;
+    size_t flushed = 0;             // staged descriptor bytes already on the device
     size_t arena_used = 0;
 
     Ctx(const tlr_plan_s *plan, void *w, hipStream_t st) : p(plan), ws(static_cast<char *>(w)), s(st) {
@@ -163,18 +165,25 @@ struct Ctx {
     double *yvec() const { return reinterpret_cast<double *>(ws + p->off_yvec); }
     double *omega() const { return reinterpret_cast<double *>(ws + p->off_omega); }
 
-    // Stage a descriptor array and copy it to the device; nullptr when full.
+    // Stage a descriptor array; it reaches the device at the next flush()
+    // (one copy for everything staged since the last one).  nullptr when full.
     template <class T>
     T *push(const T *data, size_t count) {
         const size_t bytes = align_up(sizeof(T) * std::max<size_t>(count, 1), 256);
         if (desc_used + bytes > p->desc_bytes) return nullptr;
-        char *h = hdesc + desc_used;
-        std::memcpy(h, data, sizeof(T) * count);
+        std::memcpy(hdesc + desc_used, data, sizeof(T) * count);
         T *d = reinterpret_cast<T *>(ws + p->off_desc + desc_used);
-        if (hipMemcpyAsync(d, h, sizeof(T) * count, hipMemcpyHostToDevice, s) != hipSuccess) return nullptr;
-        in_flight = true;
         desc_used += bytes;
         return d;
+    }
+    tlr_status flush() {
+        if (desc_used > flushed) {
+            TLR_HIP(hipMemcpyAsync(ws + p->off_desc + flushed, hdesc + flushed, desc_used - flushed,
+                                   hipMemcpyHostToDevice, s));
+            in_flight = true;
+            flushed = desc_used;
+        }
+        return TLR_OK;
     }
     template <class T>
     T *push(const std::vector<T> &v) {
@@ -192,6 +201,27 @@ struct Ctx {
         in_flight = false;
         ktimer_poll();
         desc_used = 0;
+        flushed = 0;
+        return TLR_OK;
+    }
+    // The four status words of every job of a wave, with one copy of the
+    // tile range they span; valid after the next stream synchronisation.
+    struct StatRead {
+        std::vector<int32_t> raw;
+        int64_t t0 = 0;
+    };
+    template <class JobT>
+    tlr_status read_stats(const std::vector<JobT> &jobs, StatRead &sr) {
+        if (jobs.empty()) return TLR_OK;
+        int64_t lo = INT64_MAX, hi = -1;
+        for (const auto &jb : jobs) {
+            const int64_t t = tile_index(jb.i, jb.j);
+            lo = std::min(lo, t);
+            hi = std::max(hi, t);
+        }
+        sr.t0 = lo;
+        sr.raw.assign((size_t)(hi - lo + 1) * 4, 0);
+        TLR_HIP(hipMemcpyAsync(sr.raw.data(), tstat(lo), sizeof(int32_t) * sr.raw.size(), hipMemcpyDeviceToHost, s));
         return TLR_OK;
     }
     tlr_status read_status(int *code) {
@@ -202,6 +232,13 @@ struct Ctx {
         return TLR_OK;
     }
 };
+
+// Launch a kernel wrapper after the staged descriptors reach the device.
+#define TLR_LAUNCH(ctx, call)     \
+    do {                          \
+        TLR_TRY((ctx).flush());   \
+        TLR_TRY(call);            \
+    } while (0)
 
 #define TLR_PUSH(ptr, ctx, vec)                          \
     auto ptr = (ctx).push(vec);                          \
@@ -238,8 +275,38 @@ tlr_status launch_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v
         const size_t cnt = std::min<size_t>(65535, v.size() - off);
         auto *d = c.push(v.data() + off, cnt);
         if (!d) return TLR_E_NOMEM;
-        TLR_TRY(gemm_batched(ta, tb, d, (int)cnt, mm, mn, c.s, v.data() + off));
+        TLR_LAUNCH(c, gemm_batched(ta, tb, d, (int)cnt, mm, mn, c.s, v.data() + off));
     }
+    return TLR_OK;
+}
+
+// A GEMM batch staged in the descriptor area, launched later: staging every
+// batch of a sequence first lets one upload carry all their descriptors.
+struct StagedGemm {
+    const GemmDesc *d = nullptr;
+    const GemmDesc *h = nullptr;
+    int count = 0, mm = 0, mn = 0;
+    bool ta = false, tb = false;
+};
+
+tlr_status stage_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v, StagedGemm *out) {
+    *out = StagedGemm{};
+    if (v.empty()) return TLR_OK;
+    if (v.size() > 65535) return TLR_E_UNSUPPORTED;
+    int mm = 0, mn = 0;
+    for (const auto &g : v) {
+        mm = std::max(mm, g.M_dev ? c.p->kmax : g.M);
+        mn = std::max(mn, g.N_dev ? c.p->rcap : g.N);
+    }
+    auto *d = c.push(v.data(), v.size());
+    if (!d) return TLR_E_NOMEM;
+    *out = StagedGemm{d, v.data(), (int)v.size(), mm, mn, ta, tb};
+    return TLR_OK;
+}
+
+tlr_status launch_staged(Ctx &c, const StagedGemm &g) {
+    if (g.count == 0 || g.mm <= 0 || g.mn <= 0) return TLR_OK;
+    TLR_LAUNCH(c, gemm_batched(g.ta, g.tb, g.d, g.count, g.mm, g.mn, c.s, g.h));
     return TLR_OK;
 }
 
@@ -314,9 +381,13 @@ tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega,
         }
     }
     if (dense) return launch_gemms(c, trans, false, g1);
-    TLR_TRY(launch_gemms(c, true, false, g1));
-    TLR_TRY(launch_gemms(c, false, false, g2));
-    return launch_gemms(c, false, false, g3);
+    StagedGemm s1, s2, s3;
+    TLR_TRY(stage_gemms(c, true, false, g1, &s1));
+    TLR_TRY(stage_gemms(c, false, false, g2, &s2));
+    TLR_TRY(stage_gemms(c, false, false, g3, &s3));
+    TLR_TRY(launch_staged(c, s1));
+    TLR_TRY(launch_staged(c, s2));
+    return launch_staged(c, s3);
 }
 
 // CholeskyQR of each job's panel (nb x k) in place, four passes: two with
@@ -330,14 +401,18 @@ tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega,
 // first basis of the range finder needs.
 tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int passes = 4) {
     const int nb = c.p->nb;
+    const size_t nj = jobs.size();
     int kmx = 0;
     for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
-    for (int it = 0; it < passes; ++it) {
-        std::vector<GemmDesc> gram;
-        std::vector<SmallDesc> sd;
-        for (auto &jb : jobs) {
-            double *Yp = on_z ? jb.Zb : jb.Yb;
-            gram.push_back(gd(Yp, nb, Yp, nb, jb.G, jb.k, jb.k, jb.k, nb, 1.0, 0.0));
+    // every pass forms the Gram matrix of the same panel: one descriptor set;
+    // the passes differ only in where R goes
+    std::vector<GemmDesc> gram;
+    std::vector<SmallDesc> sd((size_t)passes * nj);
+    for (size_t q = 0; q < nj; ++q) {
+        Job &jb = jobs[q];
+        double *Yp = on_z ? jb.Zb : jb.Yb;
+        gram.push_back(gd(Yp, nb, Yp, nb, jb.G, jb.k, jb.k, jb.k, nb, 1.0, 0.0));
+        for (int it = 0; it < passes; ++it) {
             SmallDesc d{};
             d.A = jb.G;
             d.lda = jb.k;
@@ -350,24 +425,36 @@ tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int pa
             d.k = jb.k;
             d.tile_i = jb.i;
             d.tile_j = jb.j;
-            sd.push_back(d);
+            sd[(size_t)it * nj + q] = d;
         }
-        TLR_TRY(launch_gemms(c, true, false, gram));
-        TLR_PUSH(dsd, c, sd);
-        TLR_TRY(chol_small(dsd, (int)sd.size(), kmx, it < 2 ? 1 : 2, c.params(), c.s, sd.data()));
-        TLR_TRY(trsm_rows(dsd, (int)sd.size(), nb, kmx, c.s, sd.data()));
     }
+    StagedGemm sg;
+    TLR_TRY(stage_gemms(c, true, false, gram, &sg));
+    TLR_PUSH(dsd, c, sd);
+    StagedGemm sa, sb, sc;
+    std::vector<GemmDesc> a, b, d2;
     if (want_r) {
         // Rt = R4 R3 R2 R1, accumulated through T
-        std::vector<GemmDesc> a, b, d2;
         for (auto &jb : jobs) {
             a.push_back(gd(jb.Rp[3], jb.k, jb.Rp[2], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
             b.push_back(gd(jb.T, jb.k, jb.Rp[1], jb.k, jb.Rt, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
             d2.push_back(gd(jb.Rt, jb.k, jb.Rp[0], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
         }
-        TLR_TRY(launch_gemms(c, false, false, a));
-        TLR_TRY(launch_gemms(c, false, false, b));
-        TLR_TRY(launch_gemms(c, false, false, d2));
+        TLR_TRY(stage_gemms(c, false, false, a, &sa));
+        TLR_TRY(stage_gemms(c, false, false, b, &sb));
+        TLR_TRY(stage_gemms(c, false, false, d2, &sc));
+    }
+    for (int it = 0; it < passes; ++it) {
+        const SmallDesc *dp = dsd + (size_t)it * nj;
+        const SmallDesc *hp = sd.data() + (size_t)it * nj;
+        TLR_TRY(launch_staged(c, sg));
+        TLR_LAUNCH(c, chol_small(dp, (int)nj, kmx, it < 2 ? 1 : 2, c.params(), c.s, hp));
+        TLR_LAUNCH(c, trsm_rows(dp, (int)nj, nb, kmx, c.s, hp));
+    }
+    if (want_r) {
+        TLR_TRY(launch_staged(c, sa));
+        TLR_TRY(launch_staged(c, sb));
+        TLR_TRY(launch_staged(c, sc));
         for (auto &jb : jobs) std::swap(jb.Rt, jb.T);
     }
     return TLR_OK;
@@ -422,7 +509,7 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, in
             sq.push_back(d);
         }
         TLR_PUSH(dsq, c, sq);
-        TLR_TRY(qrcp_trunc(dsq, (int)sq.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s));
+        TLR_LAUNCH(c, qrcp_trunc(dsq, (int)sq.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s));
         std::vector<GemmDesc> gu2, gv2;
         for (auto &jb : jobs) {
             GemmDesc a = gd(jb.Yb, nb, jb.Xs, jb.k, jb.Uout, nb, nb, 0, jb.k, 1.0, 0.0);
@@ -454,7 +541,7 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, in
         sd.push_back(d);
     }
     TLR_PUSH(dsd, c, sd);
-    TLR_TRY(jacobi_svd(dsd, (int)sd.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s));
+    TLR_LAUNCH(c, jacobi_svd(dsd, (int)sd.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s));
     std::vector<GemmDesc> gu, gp, gv;
     for (auto &jb : jobs) {
         GemmDesc a = gd(jb.Yb, nb, jb.Xs, jb.k, jb.Uout, nb, nb, 0, jb.k, 1.0, 0.0);
@@ -487,9 +574,10 @@ tlr_status make_dense(Ctx &c, const std::vector<std::pair<int, int>> &tiles, con
         c.dflag[(size_t)i * c.p->nt + j] = 1;
     }
     TLR_PUSH(dcp, c, cps);
-    TLR_TRY(copy_batched(dcp, (int)cps.size(), (int64_t)nb * nb, c.s));
+    TLR_LAUNCH(c, copy_batched(dcp, (int)cps.size(), (int64_t)nb * nb, c.s));
     TLR_PUSH(did, c, ids);
-    return identity_batched(did, (int)ids.size(), nb, c.s);
+    TLR_LAUNCH(c, identity_batched(did, (int)ids.size(), nb, c.s));
+    return TLR_OK;
 }
 
 int tile_rows(const tlr_plan_s *p, int i) {
@@ -633,7 +721,7 @@ tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws,
     std::vector<GenDesc> g;
     for (int k = 0; k < p->nt; ++k) g.push_back(GenDesc{c.diag(k), k * p->nb, k * p->nb, p->nb, 1});
     TLR_PUSH(dg, c, g);
-    TLR_TRY(gen_tiles_launch(dg, (int)g.size(), p->nb, p->n, c.x(), c.y(), mc, s));
+    TLR_LAUNCH(c, gen_tiles_launch(dg, (int)g.size(), p->nb, p->n, c.x(), c.y(), mc, s));
     TLR_TRY(gaussian_fill(c.omega(), (int64_t)p->nb * p->kmax, kSketchSeed, s));
     TLR_HIP(hipStreamSynchronize(s));  // host descriptors above go out of scope
     return TLR_OK;
@@ -701,13 +789,15 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
                 if (jobs.size() >= (size_t)kMaxWave) break;
             }
             TLR_PUSH(dg, c, gens);
-            TLR_TRY(gen_tiles_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), mc, s));
+            TLR_LAUNCH(c, gen_tiles_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), mc, s));
             TLR_TRY(rsvd(c, jobs, tol, nullptr, 0, d_ranks != nullptr, q1_passes(p, hb.dp.sigma2, tol)));
-            std::vector<int32_t> st(4 * jobs.size());
-            // gather the per-tile status words
-            for (size_t q = 0; q < jobs.size(); ++q)
-                TLR_HIP(hipMemcpyAsync(&st[4 * q], jobs[q].stat, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            Ctx::StatRead sr;
+            TLR_TRY(c.read_stats(jobs, sr));
             TLR_TRY(c.sync_reset());
+            std::vector<int32_t> st(4 * jobs.size());
+            for (size_t q = 0; q < jobs.size(); ++q)
+                std::memcpy(&st[4 * q], &sr.raw[(size_t)(tile_index(jobs[q].i, jobs[q].j) - sr.t0) * 4],
+                            4 * sizeof(int32_t));
             if (debug_enabled()) {
                 int code = 0;
                 TLR_TRY(c.read_status(&code));
@@ -813,7 +903,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                 mxw = std::max<int64_t>(mxw, (int64_t)rk * nb);
             }
             TLR_PUSH(dcp, c, cps);
-            TLR_TRY(copy_batched(dcp, (int)cps.size(), mxw, s));
+            TLR_LAUNCH(c, copy_batched(dcp, (int)cps.size(), mxw, s));
             std::vector<GemmDesc> gdg{gd(Xd, nb, Yj, nb, c.diag(j), nb, nb, nb, Rj, -1.0, 1.0)};
             TLR_TRY(launch_gemms(c, false, true, gdg));
         }
@@ -822,7 +912,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             std::vector<GemmDesc> pd((size_t)cdiv(nb, 64));
             potrf_tile_descs(c.diag(j), nb, pd.data());
             TLR_PUSH(dpd, c, pd);
-            TLR_TRY(potrf_tile(c.diag(j), nb, j, c.params(), dpd, s));
+            TLR_LAUNCH(c, potrf_tile(c.diag(j), nb, j, c.params(), dpd, s));
         }
         // Schur complement of the tiles below, re-compressed once
         std::vector<int> rows;
@@ -931,10 +1021,13 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                     }
                     if (!jobs.empty())
                         TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, false, q1_passes(p, hb.dp.sigma2, tol)));
+                    Ctx::StatRead sr;
+                    TLR_TRY(c.read_stats(jobs, sr));
+                    TLR_TRY(c.sync_reset());
                     std::vector<int32_t> st(4 * jobs.size());
                     for (size_t q = 0; q < jobs.size(); ++q)
-                        TLR_HIP(hipMemcpyAsync(&st[4 * q], jobs[q].stat, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                    TLR_TRY(c.sync_reset());
+                        std::memcpy(&st[4 * q], &sr.raw[(size_t)(tile_index(jobs[q].i, jobs[q].j) - sr.t0) * 4],
+                                    4 * sizeof(int32_t));
                     if (debug_enabled()) {
                         for (size_t q = 0; q < jobs.size(); ++q)
                             std::fprintf(stderr, "potrf col %d tile (%d,%d) R=%d k=%d r_old=%d write=%d num=%d flag=%d\n", j,
@@ -964,7 +1057,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                     }
                     if (!keep.empty()) {
                         TLR_PUSH(dkp, c, keep);
-                        TLR_TRY(copy_batched(dkp, (int)keep.size(), keep_max, s));
+                        TLR_LAUNCH(c, copy_batched(dkp, (int)keep.size(), keep_max, s));
                     }
                     if (!conv.empty()) {  // over the cap: keep the Schur complement dense
                         TLR_TRY(schur_dense(conv));
@@ -1006,7 +1099,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             GemmDesc *dg = reinterpret_cast<GemmDesc *>(c.ws + p->off_desc + c.desc_used);
             if (hg.size() < sd.size() * nblk) hg.resize(sd.size() * nblk);
             c.desc_used += need;
-            TLR_TRY(trsm_left_lower(c.diag(j), nb, dsd, sd.data(), (int)sd.size(), maxc, dg, hg.data(), s));
+            TLR_LAUNCH(c, trsm_left_lower(c.diag(j), nb, dsd, sd.data(), (int)sd.size(), maxc, dg, hg.data(), s));
         }
         TLR_TRY(c.sync_reset());
     }
@@ -1046,7 +1139,7 @@ tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_byt
     for (int j = 0; j < nt; ++j) {
         TLR_TRY(trsv_tile(c.diag(j), nb, c.yvec() + (int64_t)j * nb, c.params(), s));
         const int count = first[j + 1] - first[j];
-        if (count > 0) TLR_TRY(lr_gemv(dv + gb * first[j], count, nb, c.params(), s));
+        if (count > 0) TLR_LAUNCH(c, lr_gemv(dv + gb * first[j], count, nb, c.params(), s));
     }
     TLR_TRY(logdet_quad(c.diag(0), nb, nt, p->n, c.yvec(), c.params(), d_out, s));
     TLR_HIP(hipStreamSynchronize(s));
