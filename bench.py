@@ -100,6 +100,7 @@ def roofline(stats, workload: str):
     return {"kernel": top["name"], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": measured_traffic(top["name"], workload),
             "avg_launch_us": 1e3 * top["total_ms"] / max(top["launches"], 1), "launches": top["launches"],
+            "exact_launches": per, "exact_avg_launch_us": 1e3 * top["exact_ms"] / per,
             "algorithmic_bytes_per_launch": top["bytes"] / per, "algorithmic_flops_per_launch": top["flops"] / per,
             "share_of_kernel_time": top["total_ms"] / sum(s["total_ms"] for s in stats)}
 
