@@ -13,7 +13,7 @@
 //
 // One step b of the factorisation:
 //   1. one wave factors the diagonal tile in registers (lane r holds row r;
-//      the pivot comes by readlane, each new column goes round through LDS);
+//      the pivot comes by readlane, each new column by DPP row broadcast);
 //   2. every row of the panel below is solved against it (one thread a row);
 //   3. every trailing tile (i, j), b < j <= i, takes A_ij -= L_ib L_jb^T with
 //      four v_mfma_f64_16x16x4 (one wave a tile).
@@ -26,6 +26,7 @@
 
 #include "kernels.h"
 #include "ktimer.h"
+#include "lanes.h"
 
 namespace tlr {
 namespace {
@@ -44,14 +45,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __host__ inline int tri(int i) { return i * (i + 1) / 2; }
 
-// Broadcast of lane l's double to the whole wave (two v_readlane; l uniform).
-__device__ inline double readlane_d(double v, int l) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -65,7 +58,6 @@ __device__ inline double wave_max(double v) {
 // Factor the tiles in TS (tile rows T); returns the failing column + 1, or 0.
 template <bool LDS>
 __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, int *s_fail) {
-    __shared__ double colb[64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll 1
     for (int b = 0; b < T; ++b) {
@@ -99,16 +91,12 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
                 }
                 const double lrc = (r == c) ? lcc : ((r > c) ? a[c] * iv : 0.0);
                 a[c] = lrc;
-                // the column goes through LDS (one write, all reads in flight
-                // together); LDS operations of one wave complete in order
-                colb[lane] = lrc;
-                __builtin_amdgcn_wave_barrier();
+                // entry (q, c) of the new column sits in lane q of every row
                 double lq[kT];
 #pragma unroll
-                for (int q = c + 1; q < kT; ++q) lq[q] = colb[q];
+                for (int q = c + 1; q < kT; ++q) lq[q] = row_bcast_at(lrc, q);
 #pragma unroll
                 for (int q = c + 1; q < kT; ++q) a[q] -= lrc * lq[q];
-                __builtin_amdgcn_wave_barrier();
                 if (lane == c) inv[c] = iv;
             }
             if (lane < kT) {
@@ -312,8 +300,8 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restr
             const double rjl = Rd[j * kTP + li];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                // x_j of this lane's row: column j sits in lane 16 g + j of row group g
-                const double x = __shfl(acc[q] * iv, (lane & 48) + j, 64);
+                // x_j of this lane's row: column j sits in lane j of its row of 16
+                const double x = row_bcast_at(acc[q] * iv, j);
                 if (li == j)
                     acc[q] = x;
                 else if (li > j)

@@ -7,6 +7,7 @@
 
 #include "kernels.h"
 #include "ktimer.h"
+#include "lanes.h"
 
 namespace tlr {
 namespace {
@@ -329,19 +330,48 @@ __device__ void qrcp_trunc(double *M, int ld, int k, double tol2, double *cn, do
 // Register-resident variant for k <= 16 RPS and k <= 4 NW CPG (NW waves).
 // The matrix is spread over 4 NW column groups of 16 lanes (a quarter-wave):
 // group g owns columns g + 4 NW cc (cc < CPG), its lane s the rows s + 16 rr
-// (rr < RPS), so a column's reductions are four shuffles inside its group.
+// (rr < RPS), so a column's reductions are four DPP steps inside its group.
 // Columns are never swapped: the pivot of step c is frozen in place (rows < c
 // hold its column of R, row c the diagonal alpha_c) and its Householder
 // vector is kept in V (k x k scratch, column c).  Same arithmetic as
 // qrcp_trunc (pivot = largest remaining norm, smallest index on ties; stop
 // when the remaining Frobenius norm is <= tol), so Y = B^T comes straight from
 // the registers and Q1 is accumulated in registers from V.
-__device__ inline double red16(double v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
-    v += __shfl_xor(v, 8, 64);
-    return v;
+// (sum, largest value with the smallest index on ties) over the wave: a DPP
+// butterfly inside each row of 16 lanes, then the four rows by readlane.
+template <int CTRL>
+__device__ __forceinline__ void pivot_step(double &rem, double &best, int &bj) {
+    rem += dpp_d<CTRL>(rem);
+    const double ob = dpp_d<CTRL>(best);
+    const int oj = dpp_i<CTRL>(bj);
+    if (ob > best || (ob == best && oj < bj)) {
+        best = ob;
+        bj = oj;
+    }
+}
+
+__device__ __forceinline__ void pivot_reduce(double &rem, double &best, int &bj) {
+    pivot_step<kDppXor1>(rem, best, bj);
+    pivot_step<kDppXor2>(rem, best, bj);
+    pivot_step<kDppHalfMirror>(rem, best, bj);
+    pivot_step<kDppMirror>(rem, best, bj);
+    double rs[4], bs[4];
+    int js[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        rs[q] = readlane_d(rem, 16 * q);
+        bs[q] = readlane_d(best, 16 * q);
+        js[q] = __builtin_amdgcn_readlane(bj, 16 * q);
+    }
+    rem = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+    best = bs[0];
+    bj = js[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+        if (bs[q] > best || (bs[q] == best && js[q] < bj)) {
+            best = bs[q];
+            bj = js[q];
+        }
 }
 
 template <int NW, int CPG, int RPS>
@@ -395,15 +425,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
             best = cn[tid];
             bj = tid;
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            rem += __shfl_xor(rem, off, 64);
-            const double ob = __shfl_xor(best, off, 64);
-            const int oj = __shfl_xor(bj, off, 64);
-            if (ob > best || (ob == best && oj < bj)) {
-                best = ob;
-                bj = oj;
-            }
-        }
+        pivot_reduce(rem, best, bj);
         if (lane == 0) {
             redv[wave] = rem;
             redv[NW + wave] = best;

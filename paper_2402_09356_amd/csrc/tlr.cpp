@@ -362,6 +362,16 @@ tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega,
     const int nb = c.p->nb;
     std::vector<GemmDesc> g1, g2, g3;
     const bool dense = jobs.front().A != nullptr;
+    // Yj^T W is the same for every job of the column (W is one matrix, a job
+    // of width k reads its first k columns): form it once, at the widest
+    // job's width, in that job's F, and let every job read its prefix.
+    const Job *shared_f = nullptr;
+    if (!dense && from_omega && !trans) {
+        shared_f = &jobs.front();
+        for (auto &jb : jobs)
+            if (jb.k > shared_f->k) shared_f = &jb;
+        g1.push_back(gd(Yj, nb, c.omega(), nb, shared_f->F, std::max(Rj, 1), Rj, shared_f->k, nb, 1.0, 0.0));
+    }
     for (auto &jb : jobs) {
         const double *in = from_omega ? c.omega() : (into_z ? jb.Yb : jb.Zb);
         double *out = into_z ? jb.Zb : jb.Yb;
@@ -371,13 +381,14 @@ tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega,
             // H = (trans ? U : V)^T in ; F = (trans ? Xi : Yj)^T in
             const double *left = trans ? jb.Uop : jb.Vop;
             const double *big = trans ? jb.Xi : Yj;
+            double *F = shared_f ? shared_f->F : jb.F;
             g1.push_back(gd(left, nb, in, nb, jb.H, std::max(jb.r, 1), jb.r, jb.k, nb, 1.0, 0.0));
-            g1.push_back(gd(big, nb, in, nb, jb.F, std::max(Rj, 1), Rj, jb.k, nb, 1.0, 0.0));
+            if (!shared_f) g1.push_back(gd(big, nb, in, nb, F, std::max(Rj, 1), Rj, jb.k, nb, 1.0, 0.0));
             // out = (trans ? V : U) H ; out -= (trans ? Yj : Xi) F
             const double *right = trans ? jb.Vop : jb.Uop;
             const double *big2 = trans ? Yj : jb.Xi;
             g2.push_back(gd(right, nb, jb.H, std::max(jb.r, 1), out, nb, nb, jb.k, jb.r, 1.0, 0.0));
-            g3.push_back(gd(big2, nb, jb.F, std::max(Rj, 1), out, nb, nb, jb.k, Rj, -1.0, 1.0));
+            g3.push_back(gd(big2, nb, F, std::max(Rj, 1), out, nb, nb, jb.k, Rj, -1.0, 1.0));
         }
     }
     if (dense) return launch_gemms(c, trans, false, g1);
