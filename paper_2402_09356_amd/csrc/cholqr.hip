@@ -2,7 +2,8 @@
 //  * k_chol_small: Cholesky of a k x k Gram matrix (shifted CholeskyQR,
 //    Fukaya, Kannan, Nakatsukasa, Zhang, Yamamoto, SIAM J. Sci. Comput. 2020;
 //    deflation of null directions), right-looking over 16 x 16 tiles;
-//  * k_trsm_rows: Y <- Y R^-1 for the m x k panel, 16 columns at a time.
+//  * k_trsm_rows: Y <- Y R^-1 for the m x k panel, 16 columns at a time
+//    (the row block held in LDS; k_trsm_rows_wide for k above 192).
 //
 // Tiles.  The lower triangle is held as 16 x 16 tiles, tile (i, j), i >= j,
 // at index i(i+1)/2 + j, each stored column-major with a column pitch of 17
@@ -22,6 +23,7 @@
 // step fails (singular to working precision); with defl > 0 a pivot <= defl
 // is a dead direction whose whole column of L is zero, so the row solve
 // writes a zero column of Q there.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -74,21 +76,15 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
             for (int c = 0; c < kT; ++c) {
                 const double piv = readlane_d(a[c], c);
                 const int gc = kT * b + c;
-                double lcc, iv;
-                if (gc >= k) {  // padding
-                    lcc = 1.0;
-                    iv = 1.0;
-                } else if (!isfinite(piv) || (defl == 0.0 && !(piv > kPivotLoss * readlane_d(dstart, c)))) {
-                    if (!fail) fail = gc + 1;
-                    lcc = 0.0;
-                    iv = 0.0;
-                } else if (defl > 0.0 && piv <= defl) {
-                    lcc = 0.0;  // dead direction
-                    iv = 0.0;
-                } else {
-                    iv = rsqrt(piv);
-                    lcc = piv * iv;
-                }
+                // the cases resolve by selects, off the pivot's critical path:
+                // padding (1), failure or dead direction (0), else sqrt(piv)
+                const double ivr = rsqrt(piv);
+                const bool pad = gc >= k;
+                const bool bad = !isfinite(piv) || (defl == 0.0 && !(piv > kPivotLoss * readlane_d(dstart, c)));
+                const bool zero = bad || (defl > 0.0 && piv <= defl);
+                if (bad && !pad && !fail) fail = gc + 1;
+                const double iv = pad ? 1.0 : (zero ? 0.0 : ivr);
+                const double lcc = pad ? 1.0 : (zero ? 0.0 : piv * ivr);
                 const double lrc = (r == c) ? lcc : ((r > c) ? a[c] * iv : 0.0);
                 a[c] = lrc;
                 // entry (q, c) of the new column sits in lane q of every row
@@ -118,12 +114,14 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
             double a[kT];
 #pragma unroll
             for (int q = 0; q < kT; ++q) a[q] = P[r + kTP * q];
+            // column-oriented: each entry takes the same subtractions in the
+            // same order as a row dot product, with a short dependent chain
 #pragma unroll
             for (int c = 0; c < kT; ++c) {
-                double s = a[c];
+                const double xc = a[c] * inv[c];
+                a[c] = xc;
 #pragma unroll
-                for (int q = 0; q < c; ++q) s -= a[q] * D[c + kTP * q];
-                a[c] = s * inv[c];
+                for (int q = c + 1; q < kT; ++q) a[q] -= xc * D[q + kTP * c];
             }
 #pragma unroll
             for (int q = 0; q < kT; ++q) P[r + kTP * q] = a[q];
@@ -132,26 +130,51 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
         // 3. trailing tiles
         const int count = tri(n);
         const int li = lane & 15, lg = lane >> 4;
-#pragma unroll 1
-        for (int t = wave; t < count; t += kThreads / 64) {
+        // two tiles a wave at a time: their operand reads and MFMA chains
+        // are independent and overlap
+        auto tile_of = [&](int t, int &i, int &j) {
             int ip = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
             while (tri(ip + 1) <= t) ++ip;
             while (tri(ip) > t) --ip;
-            const int i = b + 1 + ip, j = b + 1 + (t - tri(ip));
-            double *C = TS + (tri(i) + j) * kTW;
-            const double *Li = TS + (tri(i) + b) * kTW;
-            const double *Lj = TS + (tri(j) + b) * kTW;
-            v4d acc;
+            i = b + 1 + ip;
+            j = b + 1 + (t - tri(ip));
+        };
+        constexpr int kW = kThreads / 64;
+#pragma unroll 1
+        for (int t = wave; t < count; t += 2 * kW) {
+            const bool two = t + kW < count;
+            int i1, j1, i2, j2;
+            tile_of(t, i1, j1);
+            tile_of(two ? t + kW : t, i2, j2);
+            double *C1 = TS + (tri(i1) + j1) * kTW;
+            double *C2 = TS + (tri(i2) + j2) * kTW;
+            const double *L1i = TS + (tri(i1) + b) * kTW, *L1j = TS + (tri(j1) + b) * kTW;
+            const double *L2i = TS + (tri(i2) + b) * kTW, *L2j = TS + (tri(j2) + b) * kTW;
+            v4d acc1, acc2;
+            double a1[4], b1[4], a2[4], b2[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = C[(lg + 4 * q) + kTP * li];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const double av = -Li[li + kTP * (4 * s + lg)];
-                const double bv = Lj[li + kTP * (4 * s + lg)];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            for (int q = 0; q < 4; ++q) {
+                acc1[q] = C1[(lg + 4 * q) + kTP * li];
+                acc2[q] = C2[(lg + 4 * q) + kTP * li];
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) C[(lg + 4 * q) + kTP * li] = acc[q];
+            for (int s = 0; s < 4; ++s) {
+                a1[s] = -L1i[li + kTP * (4 * s + lg)];
+                b1[s] = L1j[li + kTP * (4 * s + lg)];
+                a2[s] = -L2i[li + kTP * (4 * s + lg)];
+                b2[s] = L2j[li + kTP * (4 * s + lg)];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], acc1, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], b2[s], acc2, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) C1[(lg + 4 * q) + kTP * li] = acc1[q];
+            if (two) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) C2[(lg + 4 * q) + kTP * li] = acc2[q];
+            }
         }
         __syncthreads();
     }
@@ -162,26 +185,38 @@ template <bool LDS>
 __device__ __forceinline__ void load_tiles(double *TS, int T, int k, const double *A, int64_t lda, double shift) {
     const int tid = threadIdx.x;
     const int r = tid & 15, c = tid >> 4;  // 256 threads: one tile per pass
+    const int nt = tri(T);
+    int ti = 0, tj = 0;  // tile of the batch's first index
+    // sixteen tiles a batch: their loads are in flight together
 #pragma unroll 1
-    for (int ti = 0, t = 0; ti < T; ++ti)
-        for (int tj = 0; tj <= ti; ++tj, ++t) {
+    for (int t0 = 0; t0 < nt; t0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
             const int gr = kT * ti + r, gc = kT * tj + c;
-            double v;
             if (gr < k && gc < k)
-                v = (gr >= gc) ? A[gr + (int64_t)gc * lda] + ((gr == gc) ? shift : 0.0) : 0.0;
+                v[u] = (gr >= gc) ? A[gr + (int64_t)gc * lda] + ((gr == gc) ? shift : 0.0) : 0.0;
             else
-                v = (gr == gc) ? 1.0 : 0.0;
-            TS[t * kTW + r + kTP * c] = v;
+                v[u] = (gr == gc) ? 1.0 : 0.0;
+            if (++tj > ti) {
+                ++ti;
+                tj = 0;
+            }
         }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (t0 + u < nt) TS[(t0 + u) * kTW + r + kTP * c] = v[u];
+    }
 }
 
 __device__ __forceinline__ void store_r(const double *TS, int k, double *R, int64_t ldr) {
-    for (int e = threadIdx.x; e < k * k; e += kThreads) {
-        const int r = e % k, q = e / k;
-        double v = 0.0;
-        if (r <= q) v = TS[(tri(q >> 4) + (r >> 4)) * kTW + (q & 15) + kTP * (r & 15)];
-        R[r + (int64_t)q * ldr] = v;
-    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = wave; q < k; q += kThreads / 64)
+        for (int r = lane; r < k; r += 64) {
+            double v = 0.0;
+            if (r <= q) v = TS[(tri(q >> 4) + (r >> 4)) * kTW + (q & 15) + kTP * (r & 15)];
+            R[r + (int64_t)q * ldr] = v;
+        }
 }
 
 __global__ __launch_bounds__(kThreads) void k_chol_small(const SmallDesc *__restrict__ descs, int mode,
@@ -240,20 +275,151 @@ __global__ __launch_bounds__(kThreads) void k_chol_small(const SmallDesc *__rest
     }
 }
 
-// Y (m x k, ldy) <- Y R^-1, R upper triangular (k x k, ldr).  A work-group of
-// four waves owns 64 rows, a wave 16 of them.  Column block b: the R block
-// R[0 : 16b+16, 16b : 16b+16] is staged in LDS; each wave takes its 16 x 16
-// block of Y, subtracts X[:, :16b] R[:16b, block] with MFMA (X read back from
-// Y, where the earlier blocks were written), and solves against the diagonal
-// block column by column across the lanes.  A zero diagonal of R (dead
-// direction) gives a zero column.
-__global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restrict__ descs) {
+// Y (m x k, ldy) <- Y R^-1, R upper triangular (k x k, ldr), for k <= 192.  A
+// work-group of four waves owns 64 rows, a wave 16 of them; the group's 64 x k
+// block of Y is read into LDS once, solved there and written back once, so the
+// only global reads inside the column loop are the blocks of R, each fetched
+// one block ahead.  Column block b: R[0 : 16b+16, 16b : 16b+16] is staged in
+// LDS; each wave takes its 16 x 16 block, subtracts X[:, :16b] R[:16b, block]
+// with MFMA (X from the LDS copy, where the earlier blocks were solved), and
+// solves against the diagonal block one row a lane.  A zero diagonal of R
+// (dead direction) gives a zero column.
+constexpr int kTrsmLdsK = 192;
+constexpr int kYP = 65;  // LDS pitch of a column of the 64-row block
+
+// kcap: the launch's largest k up to 192, padded to 16 (sizes the LDS).
+__global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restrict__ descs, int kcap) {
+    extern __shared__ double smem[];
+    const SmallDesc d = descs[blockIdx.y];
+    const int k = d.k_dev ? *d.k_dev : d.k;
+    const int m = d.m;
+    const int r0 = blockIdx.x * 64;
+    if (k <= 0 || k > kcap || r0 >= m) return;
+    double *Ys = smem;               // 64 x kcap, column pitch kYP
+    double *Rb = smem + kYP * kcap;  // kcap x 16, row pitch kTP
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int T = (k + kT - 1) / kT;
+    double *__restrict__ Y = d.Y;
+    const double *__restrict__ R = d.R;
+    const int64_t ldy = d.ldy, ldr = d.ldr;
+    {
+        const int row = r0 + (tid & 63);
+        const bool rok = row < m;
+        const int kp = kT * T;
+        // eight columns a batch per thread (four columns a pass of the group)
+#pragma unroll 1
+        for (int c0 = 0; c0 < kp; c0 += 32) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int col = c0 + 4 * u + (tid >> 6);
+                v[u] = (rok && col < k) ? Y[row + (int64_t)col * ldy] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int col = c0 + 4 * u + (tid >> 6);
+                if (col < kp) Ys[col * kYP + (tid & 63)] = v[u];
+            }
+        }
+    }
+    const int wr = kT * wave;  // this wave's first row in the block
+    __shared__ double invd[kT];
+    // R block b, R[0 : 16b+16, 16b : 16b+16], goes through registers: its
+    // loads are issued one block ahead, behind the current block's arithmetic
+    constexpr int kRv = kTrsmLdsK / kT;
+    double rv[kRv];
+    auto load_r = [&](int b) {
+        const int rows = kT * b + kT;
+#pragma unroll
+        for (int u = 0; u < kRv; ++u) {
+            const int e = tid + kThreads * u, q = e >> 4, j = e & 15, gc = kT * b + j;
+            rv[u] = (q < rows && q < k && gc < k) ? R[q + (int64_t)gc * ldr] : ((q == gc) ? 1.0 : 0.0);
+        }
+    };
+    load_r(0);
+    for (int b = 0; b < T; ++b) {
+        __syncthreads();  // Ys loaded / the previous block's Rb consumed
+        {
+            const int rows = kT * b + kT;
+#pragma unroll
+            for (int u = 0; u < kRv; ++u) {
+                const int e = tid + kThreads * u, q = e >> 4, j = e & 15;
+                if (q < rows) Rb[q * kTP + j] = rv[u];
+                if (q == kT * b + j) invd[j] = (rv[u] != 0.0) ? 1.0 / rv[u] : 0.0;
+            }
+        }
+        __syncthreads();
+        if (b + 1 < T) load_r(b + 1);
+        const int col = kT * b + li;
+        v4d acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = Ys[col * kYP + wr + lg + 4 * q];
+        // 4b K-steps of four (a multiple of four): eight at a time, their
+        // operand reads issued together, then the last four if any
+        const int ns = 4 * b;
+        int s0 = 0;
+        for (; s0 + 8 <= ns; s0 += 8) {
+            double av[8], bv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kap = 4 * (s0 + u) + lg;
+                av[u] = -Ys[kap * kYP + wr + li];
+                bv[u] = Rb[kap * kTP + li];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+        if (s0 < ns) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kap = 4 * (s0 + u) + lg;
+                av[u] = -Ys[kap * kYP + wr + li];
+                bv[u] = Rb[kap * kTP + li];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ys[col * kYP + wr + lg + 4 * q] = acc[q];
+        // diagonal block: lane li of the first row of 16 solves row wr + li
+        // left to right in registers (LDS operations of one wave complete in
+        // order, so it reads the values just written)
+        if (lg == 0) {
+            const double *Rd = Rb + (kT * b) * kTP;  // rows 16b.. of the staged block
+            double y[kT];
+#pragma unroll
+            for (int j = 0; j < kT; ++j) y[j] = Ys[(kT * b + j) * kYP + wr + li];
+#pragma unroll
+            for (int j = 0; j < kT; ++j) {
+                const double x = y[j] * invd[j];
+                y[j] = x;
+#pragma unroll
+                for (int l = j + 1; l < kT; ++l) y[l] -= x * Rd[j * kTP + l];
+            }
+#pragma unroll
+            for (int j = 0; j < kT; ++j) Ys[(kT * b + j) * kYP + wr + li] = y[j];
+        }
+    }
+    __syncthreads();
+    {
+        const int row = r0 + (tid & 63);
+        if (row < m)
+#pragma unroll 4
+            for (int col = tid >> 6; col < k; col += 4) Y[row + (int64_t)col * ldy] = Ys[col * kYP + (tid & 63)];
+    }
+}
+
+// The same for k > 192, with Y read from and written to global memory (the
+// earlier blocks' X is read back from Y).
+__global__ __launch_bounds__(kThreads) void k_trsm_rows_wide(const SmallDesc *__restrict__ descs) {
     extern __shared__ double Rb[];
     const SmallDesc d = descs[blockIdx.y];
     const int k = d.k_dev ? *d.k_dev : d.k;
     const int m = d.m;
     const int r0 = blockIdx.x * 64;
-    if (k <= 0 || r0 >= m) return;
+    if (k <= kTrsmLdsK || r0 >= m) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int rowbase = r0 + kT * wave;
@@ -350,9 +516,19 @@ __global__ __launch_bounds__(kThreads) void k_potrf_panel(double *A, int ld, int
     __shared__ double L[64 * 65];
     const int tid = threadIdx.x;
     if (params->status != 0) return;
-    for (int e = tid; e < 64 * 64; e += kThreads) {
-        const int r = e & 63, q = e >> 6;
-        L[r + q * 65] = (r < bs && q < bs && r >= q) ? A[(b0 + r) + (int64_t)(b0 + q) * ld] : 0.0;
+    {
+        // sixteen loads a thread, all in flight together
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + kThreads * u, r = e & 63, q = e >> 6;
+            v[u] = (r < bs && q < bs && r >= q) ? A[(b0 + r) + (int64_t)(b0 + q) * ld] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + kThreads * u, r = e & 63, q = e >> 6;
+            L[r + q * 65] = v[u];
+        }
     }
     __syncthreads();
     const int row = b0 + bs + blockIdx.x * kThreads + tid;
@@ -360,13 +536,16 @@ __global__ __launch_bounds__(kThreads) void k_potrf_panel(double *A, int ld, int
     double x[64];
 #pragma unroll
     for (int c = 0; c < 64; ++c) x[c] = (c < bs) ? A[row + (int64_t)(b0 + c) * ld] : 0.0;
+    // column-oriented: once x_c is final it is taken out of every later
+    // entry, which sees the same subtractions in the same order as a row dot
+    // product would give it, with a far shorter dependent chain
 #pragma unroll
     for (int c = 0; c < 64; ++c) {
         if (c < bs) {
-            double a = x[c];
+            const double xc = x[c] / L[c + c * 65];
+            x[c] = xc;
 #pragma unroll
-            for (int cp = 0; cp < c; ++cp) a -= x[cp] * L[c + cp * 65];
-            x[c] = a / L[c + c * 65];
+            for (int cq = c + 1; cq < 64; ++cq) x[cq] -= xc * L[cq + c * 65];
         }
     }
 #pragma unroll
@@ -432,24 +611,42 @@ tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, 
                      const SmallDesc *h_descs) {
     if (count <= 0 || max_m <= 0 || max_k <= 0) return TLR_OK;
     if (max_k > kMaxSketch) return TLR_E_UNSUPPORTED;
-    static const int cls = ktimer_class("k_trsm_rows");
+    static const int cls = ktimer_class("k_trsm_rows"), cls_w = ktimer_class("k_trsm_rows_wide");
     static const bool attr = [] {
-        return hipFuncSetAttribute(reinterpret_cast<const void *>(k_trsm_rows),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) == hipSuccess;
+        const bool a = hipFuncSetAttribute(reinterpret_cast<const void *>(k_trsm_rows),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) == hipSuccess;
+        const bool b = hipFuncSetAttribute(reinterpret_cast<const void *>(k_trsm_rows_wide),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) == hipSuccess;
+        return a && b;
     }();
     if (!attr) (void)hipGetLastError();  // launches above 64 KB will then report the limit
     (void)attr;
-    double flops = 0.0, bytes = 0.0;
+    double flops = 0.0, bytes = 0.0, flops_w = 0.0, bytes_w = 0.0;
     if (h_descs && ktimer_on())
         for (int t = 0; t < count; ++t) {
             const double k = h_descs[t].k, m = h_descs[t].m;
-            flops += m * k * k;
-            bytes += 8.0 * (2.0 * m * k + k * (k + 1.0) / 2.0);
+            const double f = m * k * k, b = 8.0 * (2.0 * m * k + k * (k + 1.0) / 2.0);
+            if (h_descs[t].k <= kTrsmLdsK) {
+                flops += f;
+                bytes += b;
+            } else {
+                flops_w += f;
+                bytes_w += b;
+            }
         }
-    const int kp = (max_k + kT - 1) / kT * kT;
-    const size_t lds = sizeof(double) * (size_t)kp * kTP;
-    KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
-    hipLaunchKernelGGL(k_trsm_rows, dim3((unsigned)cdiv(max_m, 64), count), dim3(kThreads), lds, s, d_descs);
+    const dim3 grid((unsigned)cdiv(max_m, 64), (unsigned)count);
+    {
+        const int kcap = (std::min(max_k, kTrsmLdsK) + kT - 1) / kT * kT;
+        const size_t lds = sizeof(double) * ((size_t)kYP * kcap + (size_t)kcap * kTP);
+        KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
+        hipLaunchKernelGGL(k_trsm_rows, grid, dim3(kThreads), lds, s, d_descs, kcap);
+    }
+    if (max_k > kTrsmLdsK) {
+        const int kp = (max_k + kT - 1) / kT * kT;
+        const size_t lds = sizeof(double) * (size_t)kp * kTP;
+        KTimer kt(cls_w, s, flops_w, bytes_w, h_descs != nullptr);
+        hipLaunchKernelGGL(k_trsm_rows_wide, grid, dim3(kThreads), lds, s, d_descs);
+    }
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }

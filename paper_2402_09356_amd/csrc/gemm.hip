@@ -17,6 +17,9 @@ namespace tlr {
 namespace {
 
 constexpr int BM = 32, BN = 32, BK = 16;
+// a product batch is "tall" (streaming kernels) from this many rows of C and
+// this many 64-row blocks over the batch
+constexpr int kTallM = 256, kTallBlocks = 256;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -108,6 +111,203 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *descs, int til
     }
 }
 
+// Tall products with a wider right factor, or a transposed left one: a
+// work-group owns a BM x BN block of C, its four waves a 2 x 2 grid of
+// (BM/2) x (BN/2) blocks over the whole of K.  Each 16-deep slice of op(A)
+// and op(B) is read coalesced (along whichever index is contiguous in
+// memory) into registers one slice ahead, then stored k-major in LDS, where
+// the waves read their MFMA operands.
+template <bool TA, bool TB, int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm_lds(const GemmDesc *descs, int tiles_n) {
+    constexpr int BK = 16, TM = BM / 32, TN = BN / 32;
+    constexpr int PA = BM + 1, PB = BN + 1;
+    constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+    const GemmDesc d = descs[blockIdx.y];
+    const int M = d.M_dev ? *d.M_dev : d.M;
+    const int N = d.N_dev ? *d.N_dev : d.N;
+    const int K = d.K_dev ? *d.K_dev : d.K;
+    const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    const int m0 = tm * BM, n0 = tn * BN;
+    if (m0 >= M || n0 >= N) return;
+    __shared__ double As[2][BK * PA];
+    __shared__ double Bs[2][BK * PB];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;
+    const double *__restrict__ A = d.A;
+    const double *__restrict__ B = d.B;
+    const int64_t lda = d.lda, ldb = d.ldb;
+    double ra[LA], rb[LB];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            const int e = tid + 256 * u;
+            const int m = TA ? e / BK : e % BM, k = TA ? e % BK : e / BM;
+            const int gm = m0 + m, gk = k0 + k;
+            ra[u] = (gm < M && gk < K) ? (TA ? A[gk + gm * lda] : A[gm + gk * lda]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int e = tid + 256 * u;
+            const int n = TB ? e % BN : e / BK, k = TB ? e / BN : e % BK;
+            const int gn = n0 + n, gk = k0 + k;
+            rb[u] = (gn < N && gk < K) ? (TB ? B[gn + gk * ldb] : B[gk + gn * ldb]) : 0.0;
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            const int e = tid + 256 * u;
+            const int m = TA ? e / BK : e % BM, k = TA ? e % BK : e / BM;
+            As[buf][k * PA + m] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int e = tid + 256 * u;
+            const int n = TB ? e % BN : e / BK, k = TB ? e / BN : e % BK;
+            Bs[buf][k * PB + n] = rb[u];
+        }
+    };
+    v4d acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nsl = (K + BK - 1) / BK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int sl = 0; sl < nsl; ++sl) {
+        const int buf = sl & 1;
+        if (sl + 1 < nsl) gload((sl + 1) * BK);
+        const double *as = As[buf], *bs = Bs[buf];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            double av[TM], bv[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) av[i] = as[(4 * t + lk) * PA + wm * (BM / 2) + 16 * i + li];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bv[j] = bs[(4 * t + lk) * PB + wn * (BN / 2) + 16 * j + li];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        if (sl + 1 < nsl) lstore(buf ^ 1);
+        __syncthreads();
+    }
+    double *__restrict__ C = d.C;
+    const int64_t ldc = d.ldc;
+    const double alpha = d.alpha, beta = d.beta;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm * (BM / 2) + 16 * i + lk + 4 * r;
+                const int gn = n0 + wn * (BN / 2) + 16 * j + li;
+                if (gm < M && gn < N) {
+                    double *cp = C + gm + (int64_t)gn * ldc;
+                    const double v = alpha * acc[i][j][r];
+                    *cp = (beta == 0.0) ? v : v + beta * (*cp);
+                }
+            }
+}
+
+// Tall products with a narrow right factor (N <= 64, M in the hundreds or
+// more, K long): a work-group owns 64 rows of C and every column; wave w owns
+// rows 16w..16w+15.  Each wave streams its rows of op(A) straight into
+// registers in MFMA operand layout, a 64-deep chunk of K ahead of the
+// arithmetic, so every byte of A is read once and many are in flight; the
+// chunk of B (64 x N) is shared through LDS, double-buffered.  For op(A) =
+// A^T a lane takes sixteen consecutive k (contiguous in memory) and B is read
+// from LDS with the same assignment of k to MFMA steps.
+template <bool TA, int NT>
+__global__ __launch_bounds__(256) void k_gemm_rows(const GemmDesc *descs) {
+    constexpr int KC = 64, NP = 16 * NT + 1, NBL = KC * 16 * NT / 256;
+    const GemmDesc d = descs[blockIdx.y];
+    const int M = d.M_dev ? *d.M_dev : d.M;
+    const int N = d.N_dev ? *d.N_dev : d.N;
+    const int K = d.K_dev ? *d.K_dev : d.K;
+    const int m0 = blockIdx.x * 64;
+    if (m0 >= M || N <= 0) return;
+    __shared__ double Bs[2][KC * NP];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int row = m0 + 16 * wave + li;
+    const bool rok = row < M;
+    const double *__restrict__ A = d.A;
+    const double *__restrict__ B = d.B;
+    const int64_t lda = d.lda, ldb = d.ldb;
+    double acur[16], anxt[16], bnxt[NBL];
+    auto load_a = [&](double(&dst)[16], int kc0) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int kk = kc0 + (TA ? 16 * lk + s : 4 * s + lk);
+            dst[s] = (rok && kk < K) ? (TA ? A[kk + row * lda] : A[row + kk * lda]) : 0.0;
+        }
+    };
+    auto load_b = [&](int kc0) {
+#pragma unroll
+        for (int u = 0; u < NBL; ++u) {
+            const int e = tid + 256 * u, kk = e % KC, n = e / KC;
+            bnxt[u] = (kc0 + kk < K && n < N) ? B[(kc0 + kk) + n * ldb] : 0.0;
+        }
+    };
+    auto store_b = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < NBL; ++u) {
+            const int e = tid + 256 * u, kk = e % KC, n = e / KC;
+            Bs[buf][kk * NP + n] = bnxt[u];
+        }
+    };
+    v4d acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nch = (K + KC - 1) / KC;
+    load_a(acur, 0);
+    load_b(0);
+    store_b(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) {
+            load_a(anxt, (c + 1) * KC);
+            load_b((c + 1) * KC);
+        }
+        const double *bs = Bs[buf];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int kr = TA ? 16 * lk + s : 4 * s + lk;
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[s], bs[kr * NP + 16 * j + li], acc[j], 0, 0, 0);
+        }
+        if (c + 1 < nch) {
+            store_b(buf ^ 1);
+#pragma unroll
+            for (int s = 0; s < 16; ++s) acur[s] = anxt[s];
+        }
+        __syncthreads();
+    }
+    double *__restrict__ C = d.C;
+    const int64_t ldc = d.ldc;
+    const double alpha = d.alpha, beta = d.beta;
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int gm = m0 + 16 * wave + lk + 4 * r, gn = 16 * j + li;
+            if (gm < M && gn < N) {
+                double *cp = C + gm + (int64_t)gn * ldc;
+                const double v = alpha * acc[j][r];
+                *cp = (beta == 0.0) ? v : v + beta * (*cp);
+            }
+        }
+}
+
 }  // namespace
 
 tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int count, int max_m,
@@ -127,6 +327,44 @@ tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int
             flops += 2.0 * M * N * K;
             bytes += 8.0 * (M * K + K * N + M * N * (g.beta != 0.0 ? 2.0 : 1.0));
         }
+    // tall products (many rows of C) go to the streaming kernels: a narrow
+    // N x K right factor to k_gemm_rows, a transposed left factor or a wider
+    // right one to k_gemm_lds; short ones (Gram matrices, small sketches)
+    // keep the K-split kernel, which spreads a long K over four waves
+    const int row_blocks = (int)cdiv(max_m, 64);
+    if (!trans_b && max_m >= kTallM && (int64_t)row_blocks * count >= kTallBlocks) {
+        static const int cls_r = ktimer_class("k_gemm_rows<N>"), cls_t = ktimer_class("k_gemm_lds<T,N>"),
+                         cls_w = ktimer_class("k_gemm_lds<N,N>");
+        if (!trans_a && max_n <= 64) {
+            KTimer kt(cls_r, s, flops, bytes, exact);
+            const dim3 grid((unsigned)row_blocks, (unsigned)count);
+            const int nt = (int)cdiv(max_n, 16);
+            if (nt <= 1)
+                hipLaunchKernelGGL((k_gemm_rows<false, 1>), grid, dim3(256), 0, s, d_descs);
+            else if (nt == 2)
+                hipLaunchKernelGGL((k_gemm_rows<false, 2>), grid, dim3(256), 0, s, d_descs);
+            else if (nt == 3)
+                hipLaunchKernelGGL((k_gemm_rows<false, 3>), grid, dim3(256), 0, s, d_descs);
+            else
+                hipLaunchKernelGGL((k_gemm_rows<false, 4>), grid, dim3(256), 0, s, d_descs);
+        } else {
+            KTimer kt(trans_a ? cls_t : cls_w, s, flops, bytes, exact);
+            if (trans_a && max_n > 32) {
+                const int tn = (int)cdiv(max_n, 64);
+                const dim3 grid((unsigned)(row_blocks * tn), (unsigned)count);
+                hipLaunchKernelGGL((k_gemm_lds<true, false, 64, 64>), grid, dim3(256), 0, s, d_descs, tn);
+            } else {
+                const int tn = (int)cdiv(max_n, 32);
+                const dim3 grid((unsigned)(row_blocks * tn), (unsigned)count);
+                if (trans_a)
+                    hipLaunchKernelGGL((k_gemm_lds<true, false, 64, 32>), grid, dim3(256), 0, s, d_descs, tn);
+                else
+                    hipLaunchKernelGGL((k_gemm_lds<false, false, 64, 32>), grid, dim3(256), 0, s, d_descs, tn);
+            }
+        }
+        TLR_HIP(hipGetLastError());
+        return TLR_OK;
+    }
     KTimer kt(cls[(trans_a ? 2 : 0) + (trans_b ? 1 : 0)], s, flops, bytes, exact);
     const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)count), block(256);
     if (!trans_a && !trans_b)

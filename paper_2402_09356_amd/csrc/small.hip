@@ -692,9 +692,20 @@ __global__ __launch_bounds__(64) void k_trsm_block(const double *__restrict__ L,
     const int cols = d.k_dev ? *d.k_dev : d.k;
     const int c = blockIdx.x * 64 + threadIdx.x;
     if (blockIdx.x * 64 >= cols) return;
-    for (int e = threadIdx.x; e < bs * bs; e += 64) {
-        const int r = e % bs, q = e / bs;
-        Ls[r + q * 64] = (r >= q) ? L[(b0 + r) + (int64_t)(b0 + q) * ldl] : 0.0;
+    {
+        // the block of L, lane = row, sixteen columns a batch (loads in flight together)
+        const int r = threadIdx.x;
+#pragma unroll
+        for (int q0 = 0; q0 < 64; q0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int q = q0 + u;
+                v[u] = (r < bs && q < bs && r >= q) ? L[(b0 + r) + (int64_t)(b0 + q) * ldl] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) Ls[r + (q0 + u) * 64] = v[u];
+        }
     }
     __syncthreads();
     if (c >= cols) return;
@@ -702,20 +713,15 @@ __global__ __launch_bounds__(64) void k_trsm_block(const double *__restrict__ L,
     double x[64];
 #pragma unroll
     for (int r = 0; r < 64; ++r) x[r] = (r < bs) ? y[r] : 0.0;
+    // forward substitution, column-oriented: once x_r is final it is taken
+    // out of every later row (entries below bs are zero in Ls)
 #pragma unroll
     for (int r = 0; r < 64; ++r) {
         if (r < bs) {
-            // four independent partial sums shorten the dependent chain
-            double a0 = x[r], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            const double xr = x[r] / Ls[r + r * 64];
+            x[r] = xr;
 #pragma unroll
-            for (int rp = 0; rp < r; ++rp) {
-                const double t = Ls[r + rp * 64] * x[rp];
-                if ((rp & 3) == 0) a0 -= t;
-                else if ((rp & 3) == 1) a1 -= t;
-                else if ((rp & 3) == 2) a2 -= t;
-                else a3 -= t;
-            }
-            x[r] = ((a0 + a1) + (a2 + a3)) / Ls[r + r * 64];
+            for (int rp = r + 1; rp < 64; ++rp) x[rp] -= Ls[rp + r * 64] * xr;
         }
     }
 #pragma unroll
