@@ -241,6 +241,12 @@ typedef struct tlr_kstat {
 /* Turn the timer on (nonzero) or off.  Timing adds two event records per
  * launch; it does not synchronise the stream. */
 tlr_status tlr_kstats_enable(int32_t on);
+/* Restrict timing to the kernel class called `name` (the name
+ * tlr_kstats_read reports, e.g. "k_chol_small"); NULL or "" times every
+ * class again.  Launches of other classes then carry no events at all, which
+ * keeps the timer's own cost off the untimed kernels.  Unknown names are
+ * registered (and then match nothing until such a kernel runs). */
+tlr_status tlr_kstats_select(const char *name);
 /* Wait for pending timed launches, then zero every counter. */
 tlr_status tlr_kstats_reset(void);
 /* Wait for pending timed launches and copy up to `max` entries into `out`

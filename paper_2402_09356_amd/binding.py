@@ -75,6 +75,7 @@ _SIGNATURES = {
     "tlr_kstats_enable": (I32, [I32]),
     "tlr_ranks_read": (I32, [P, P, I32, P, P]),
     "tlr_kstats_reset": (I32, []),
+    "tlr_kstats_select": (I32, [ctypes.c_char_p]),
     "tlr_kstats_read": (I32, [P, I32]),
     "tlr_diag_qrcp": (I32, [I32, I32, P, F64, P, P, P, P, P]),
 }
@@ -266,6 +267,11 @@ def diag_qrcp(mats: torch.Tensor, tol: float):
 def kstats_enable(on: bool = True):
     """Time every instrumented launch with HIP events on its stream."""
     _check(lib().tlr_kstats_enable(1 if on else 0), "tlr_kstats_enable")
+
+
+def kstats_select(name: str | None = None):
+    """Time only kernel class `name` (None: every class)."""
+    _check(lib().tlr_kstats_select(name.encode() if name else None), "tlr_kstats_select")
 
 
 def kstats_reset():

@@ -24,6 +24,10 @@ SOURCES = ["order.hip", "gensolve.hip", "gemm.hip", "small.hip", "cholqr.hip", "
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs (gfx90a and later allow it): without
+    # this the compiler keeps them in AGPRs and copies them in and out around
+    # every loop iteration of the matrix-core kernels
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     f"-I{os.path.join(ROOT, 'include')}",
 ]

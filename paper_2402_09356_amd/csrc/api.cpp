@@ -101,6 +101,11 @@ tlr_status tlr_kstats_enable(int32_t on) {
     return TLR_OK;
 }
 
+tlr_status tlr_kstats_select(const char *name) {
+    tlr::ktimer_select((name && name[0]) ? tlr::ktimer_class(name) : -1);
+    return TLR_OK;
+}
+
 tlr_status tlr_kstats_reset(void) {
     tlr::ktimer_reset();
     return TLR_OK;

@@ -187,12 +187,12 @@ __device__ __forceinline__ void load_tiles(double *TS, int T, int k, const doubl
     const int r = tid & 15, c = tid >> 4;  // 256 threads: one tile per pass
     const int nt = tri(T);
     int ti = 0, tj = 0;  // tile of the batch's first index
-    // sixteen tiles a batch: their loads are in flight together
+    // thirty-two tiles a batch: their loads are in flight together
 #pragma unroll 1
-    for (int t0 = 0; t0 < nt; t0 += 16) {
-        double v[16];
+    for (int t0 = 0; t0 < nt; t0 += 32) {
+        double v[32];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < 32; ++u) {
             const int gr = kT * ti + r, gc = kT * tj + c;
             if (gr < k && gc < k)
                 v[u] = (gr >= gc) ? A[gr + (int64_t)gc * lda] + ((gr == gc) ? shift : 0.0) : 0.0;
@@ -204,7 +204,7 @@ __device__ __forceinline__ void load_tiles(double *TS, int T, int k, const doubl
             }
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
+        for (int u = 0; u < 32; ++u)
             if (t0 + u < nt) TS[(t0 + u) * kTW + r + kTP * c] = v[u];
     }
 }
@@ -355,32 +355,25 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restr
         v4d acc;
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = Ys[col * kYP + wr + lg + 4 * q];
-        // 4b K-steps of four (a multiple of four): eight at a time, their
-        // operand reads issued together, then the last four if any
+        // 4b K-steps of four (a multiple of four), four at a time into four
+        // independent partial sums, so consecutive MFMAs do not wait on each
+        // other; the partial sums join the block at the end
         const int ns = 4 * b;
-        int s0 = 0;
-        for (; s0 + 8 <= ns; s0 += 8) {
-            double av[8], bv[8];
+        v4d part[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int kap = 4 * (s0 + u) + lg;
-                av[u] = -Ys[kap * kYP + wr + li];
-                bv[u] = Rb[kap * kTP + li];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
-        }
-        if (s0 < ns) {
+        for (int u = 0; u < 4; ++u) part[u] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int s0 = 0; s0 < ns; s0 += 4) {
             double av[4], bv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int kap = 4 * (s0 + u) + lg;
-                av[u] = -Ys[kap * kYP + wr + li];
+                av[u] = Ys[kap * kYP + wr + li];
                 bv[u] = Rb[kap * kTP + li];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+            for (int u = 0; u < 4; ++u) part[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], part[u], 0, 0, 0);
         }
+        if (ns > 0) acc -= (part[0] + part[1]) + (part[2] + part[3]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) Ys[col * kYP + wr + lg + 4 * q] = acc[q];
         // diagonal block: lane li of the first row of 16 solves row wr + li

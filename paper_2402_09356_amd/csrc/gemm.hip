@@ -216,98 +216,6 @@ __global__ __launch_bounds__(256) void k_gemm_lds(const GemmDesc *descs, int til
             }
 }
 
-// Tall products with a narrow right factor (N <= 64, M in the hundreds or
-// more, K long): a work-group owns 64 rows of C and every column; wave w owns
-// rows 16w..16w+15.  Each wave streams its rows of op(A) straight into
-// registers in MFMA operand layout, a 64-deep chunk of K ahead of the
-// arithmetic, so every byte of A is read once and many are in flight; the
-// chunk of B (64 x N) is shared through LDS, double-buffered.  For op(A) =
-// A^T a lane takes sixteen consecutive k (contiguous in memory) and B is read
-// from LDS with the same assignment of k to MFMA steps.
-template <bool TA, int NT>
-__global__ __launch_bounds__(256) void k_gemm_rows(const GemmDesc *descs) {
-    constexpr int KC = 64, NP = 16 * NT + 1, NBL = KC * 16 * NT / 256;
-    const GemmDesc d = descs[blockIdx.y];
-    const int M = d.M_dev ? *d.M_dev : d.M;
-    const int N = d.N_dev ? *d.N_dev : d.N;
-    const int K = d.K_dev ? *d.K_dev : d.K;
-    const int m0 = blockIdx.x * 64;
-    if (m0 >= M || N <= 0) return;
-    __shared__ double Bs[2][KC * NP];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int row = m0 + 16 * wave + li;
-    const bool rok = row < M;
-    const double *__restrict__ A = d.A;
-    const double *__restrict__ B = d.B;
-    const int64_t lda = d.lda, ldb = d.ldb;
-    double acur[16], anxt[16], bnxt[NBL];
-    auto load_a = [&](double(&dst)[16], int kc0) {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int kk = kc0 + (TA ? 16 * lk + s : 4 * s + lk);
-            dst[s] = (rok && kk < K) ? (TA ? A[kk + row * lda] : A[row + kk * lda]) : 0.0;
-        }
-    };
-    auto load_b = [&](int kc0) {
-#pragma unroll
-        for (int u = 0; u < NBL; ++u) {
-            const int e = tid + 256 * u, kk = e % KC, n = e / KC;
-            bnxt[u] = (kc0 + kk < K && n < N) ? B[(kc0 + kk) + n * ldb] : 0.0;
-        }
-    };
-    auto store_b = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < NBL; ++u) {
-            const int e = tid + 256 * u, kk = e % KC, n = e / KC;
-            Bs[buf][kk * NP + n] = bnxt[u];
-        }
-    };
-    v4d acc[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
-    const int nch = (K + KC - 1) / KC;
-    load_a(acur, 0);
-    load_b(0);
-    store_b(0);
-    __syncthreads();
-    for (int c = 0; c < nch; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nch) {
-            load_a(anxt, (c + 1) * KC);
-            load_b((c + 1) * KC);
-        }
-        const double *bs = Bs[buf];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int kr = TA ? 16 * lk + s : 4 * s + lk;
-#pragma unroll
-            for (int j = 0; j < NT; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[s], bs[kr * NP + 16 * j + li], acc[j], 0, 0, 0);
-        }
-        if (c + 1 < nch) {
-            store_b(buf ^ 1);
-#pragma unroll
-            for (int s = 0; s < 16; ++s) acur[s] = anxt[s];
-        }
-        __syncthreads();
-    }
-    double *__restrict__ C = d.C;
-    const int64_t ldc = d.ldc;
-    const double alpha = d.alpha, beta = d.beta;
-#pragma unroll
-    for (int j = 0; j < NT; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int gm = m0 + 16 * wave + lk + 4 * r, gn = 16 * j + li;
-            if (gm < M && gn < N) {
-                double *cp = C + gm + (int64_t)gn * ldc;
-                const double v = alpha * acc[j][r];
-                *cp = (beta == 0.0) ? v : v + beta * (*cp);
-            }
-        }
-}
-
 }  // namespace
 
 tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int count, int max_m,
@@ -327,40 +235,26 @@ tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int
             flops += 2.0 * M * N * K;
             bytes += 8.0 * (M * K + K * N + M * N * (g.beta != 0.0 ? 2.0 : 1.0));
         }
-    // tall products (many rows of C) go to the streaming kernels: a narrow
-    // N x K right factor to k_gemm_rows, a transposed left factor or a wider
-    // right one to k_gemm_lds; short ones (Gram matrices, small sketches)
-    // keep the K-split kernel, which spreads a long K over four waves
+    // tall products (many rows of C) with a transposed left factor or a
+    // right factor wider than 64 go to the LDS-staged kernel, which reads
+    // both operands along their contiguous index and needs no final
+    // reduction; the rest keep the K-split kernel, which spreads a long K
+    // over four waves (Gram matrices, narrow sketches)
     const int row_blocks = (int)cdiv(max_m, 64);
-    if (!trans_b && max_m >= kTallM && (int64_t)row_blocks * count >= kTallBlocks) {
-        static const int cls_r = ktimer_class("k_gemm_rows<N>"), cls_t = ktimer_class("k_gemm_lds<T,N>"),
-                         cls_w = ktimer_class("k_gemm_lds<N,N>");
-        if (!trans_a && max_n <= 64) {
-            KTimer kt(cls_r, s, flops, bytes, exact);
-            const dim3 grid((unsigned)row_blocks, (unsigned)count);
-            const int nt = (int)cdiv(max_n, 16);
-            if (nt <= 1)
-                hipLaunchKernelGGL((k_gemm_rows<false, 1>), grid, dim3(256), 0, s, d_descs);
-            else if (nt == 2)
-                hipLaunchKernelGGL((k_gemm_rows<false, 2>), grid, dim3(256), 0, s, d_descs);
-            else if (nt == 3)
-                hipLaunchKernelGGL((k_gemm_rows<false, 3>), grid, dim3(256), 0, s, d_descs);
-            else
-                hipLaunchKernelGGL((k_gemm_rows<false, 4>), grid, dim3(256), 0, s, d_descs);
+    if (!trans_b && (trans_a || max_n > 64) && max_m >= kTallM && (int64_t)row_blocks * count >= kTallBlocks) {
+        static const int cls_t = ktimer_class("k_gemm_lds<T,N>"), cls_w = ktimer_class("k_gemm_lds<N,N>");
+        KTimer kt(trans_a ? cls_t : cls_w, s, flops, bytes, exact);
+        if (trans_a && max_n > 32) {
+            const int tn = (int)cdiv(max_n, 64);
+            const dim3 grid((unsigned)(row_blocks * tn), (unsigned)count);
+            hipLaunchKernelGGL((k_gemm_lds<true, false, 64, 64>), grid, dim3(256), 0, s, d_descs, tn);
         } else {
-            KTimer kt(trans_a ? cls_t : cls_w, s, flops, bytes, exact);
-            if (trans_a && max_n > 32) {
-                const int tn = (int)cdiv(max_n, 64);
-                const dim3 grid((unsigned)(row_blocks * tn), (unsigned)count);
-                hipLaunchKernelGGL((k_gemm_lds<true, false, 64, 64>), grid, dim3(256), 0, s, d_descs, tn);
-            } else {
-                const int tn = (int)cdiv(max_n, 32);
-                const dim3 grid((unsigned)(row_blocks * tn), (unsigned)count);
-                if (trans_a)
-                    hipLaunchKernelGGL((k_gemm_lds<true, false, 64, 32>), grid, dim3(256), 0, s, d_descs, tn);
-                else
-                    hipLaunchKernelGGL((k_gemm_lds<false, false, 64, 32>), grid, dim3(256), 0, s, d_descs, tn);
-            }
+            const int tn = (int)cdiv(max_n, 32);
+            const dim3 grid((unsigned)(row_blocks * tn), (unsigned)count);
+            if (trans_a)
+                hipLaunchKernelGGL((k_gemm_lds<true, false, 64, 32>), grid, dim3(256), 0, s, d_descs, tn);
+            else
+                hipLaunchKernelGGL((k_gemm_lds<false, false, 64, 32>), grid, dim3(256), 0, s, d_descs, tn);
         }
         TLR_HIP(hipGetLastError());
         return TLR_OK;

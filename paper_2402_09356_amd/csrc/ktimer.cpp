@@ -22,6 +22,7 @@ struct Pending {
 struct State {
     std::mutex mu;
     std::atomic<bool> on{false};
+    std::atomic<int> sel{-1};  // the one class timed, or -1 for all
     std::vector<std::string> names;
     std::vector<KStat> stats;
     std::deque<Pending> pending;
@@ -87,6 +88,8 @@ bool ktimer_on() { return st().on.load(std::memory_order_relaxed); }
 
 void ktimer_enable(bool on) { st().on.store(on); }
 
+void ktimer_select(int cls) { st().sel.store(cls); }
+
 void ktimer_poll() {
     State &S = st();
     if (!S.on.load(std::memory_order_relaxed)) return;
@@ -118,6 +121,8 @@ KTimer::KTimer(int cls, hipStream_t s, double flops, double bytes, bool exact)
     : cls_(cls), s_(s), flops_(flops), bytes_(bytes), exact_(exact) {
     if (!ktimer_on()) return;
     State &S = st();
+    const int sel = S.sel.load(std::memory_order_relaxed);
+    if (sel >= 0 && sel != cls) return;
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> g(S.mu);

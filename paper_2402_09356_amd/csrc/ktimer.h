@@ -33,6 +33,7 @@ struct KStat {
     double bytes;
 };
 void ktimer_enable(bool on);
+void ktimer_select(int cls);  // time only this class (-1: every class)
 void ktimer_reset();
 int ktimer_read(KStat *out, int max);  // waits for every pending launch
 

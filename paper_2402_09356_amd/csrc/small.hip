@@ -546,13 +546,31 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
 #pragma unroll
         for (int rr = 0; rr < RPS; ++rr) a[cc][rr] = (sl + 16 * rr == q) ? 1.0 : 0.0;
     }
-    for (int h = r - 1; h >= 0; --h) {
+    // the reflectors go through LDS sixteen at a time, the next sixteen
+    // loaded into registers while the current ones are applied
+    constexpr int HC = 16, VL = HC * KR / NT;
+    static_assert(VL * NT == HC * KR, "reflector chunk must split evenly over the threads");
+    __shared__ double Vs[HC * KR];
+    double vbuf[VL];
+    auto vload = [&](int hc0) {
+#pragma unroll
+        for (int u = 0; u < VL; ++u) {
+            const int e = tid + NT * u, hh = e / KR, i = e - hh * KR, h = hc0 - hh;
+            vbuf[u] = (h >= 0 && i >= h && i < k) ? V[i + (int64_t)h * k] : 0.0;
+        }
+    };
+    if (r > 0) vload(r - 1);
+    for (int hc0 = r - 1; hc0 >= 0; hc0 -= HC) {
+        __syncthreads();  // the previous chunk has been applied
+#pragma unroll
+        for (int u = 0; u < VL; ++u) Vs[tid + NT * u] = vbuf[u];
+        __syncthreads();
+        if (hc0 - HC >= 0) vload(hc0 - HC);
+        const int hlo = hc0 - HC + 1 > 0 ? hc0 - HC + 1 : 0;
+    for (int h = hc0; h >= hlo; --h) {
         double vr[RPS];
 #pragma unroll
-        for (int rr = 0; rr < RPS; ++rr) {
-            const int i = sl + 16 * rr;
-            vr[rr] = (i >= h && i < k) ? V[i + (int64_t)h * k] : 0.0;
-        }
+        for (int rr = 0; rr < RPS; ++rr) vr[rr] = Vs[(hc0 - h) * KR + sl + 16 * rr];
         const double bt = bet[h];
 #pragma unroll
         for (int cc = 0; cc < CPG; ++cc) {
@@ -566,6 +584,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
                 for (int rr = 0; rr < RPS; ++rr) a[cc][rr] -= t * vr[rr];
             }
         }
+    }
     }
 #pragma unroll
     for (int cc = 0; cc < CPG; ++cc) {

@@ -93,6 +93,55 @@ class PinnedPool {
     std::vector<std::pair<char *, size_t>> free_;
 };
 
+// Side streams (default priority) with the two events that order work on
+// them against a context's main stream; per device, kept for the life of the
+// process and handed out to one context at a time.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t from_main = nullptr, from_side = nullptr;
+    int dev = -1;
+};
+
+class SidePool {
+  public:
+    bool get(SideStream *out) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return false;
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            for (size_t i = 0; i < free_.size(); ++i)
+                if (free_[i].dev == dev) {
+                    *out = free_[i];
+                    free_.erase(free_.begin() + (std::ptrdiff_t)i);
+                    return true;
+                }
+        }
+        SideStream n;
+        n.dev = dev;
+        if (hipStreamCreateWithFlags(&n.s, hipStreamNonBlocking) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&n.from_main, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&n.from_side, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;  // leaked on this rare path; the context then stays on one stream
+        }
+        *out = n;
+        return true;
+    }
+    void put(const SideStream &st) {
+        std::lock_guard<std::mutex> g(mu_);
+        free_.push_back(st);
+    }
+
+  private:
+    std::mutex mu_;
+    std::vector<SideStream> free_;
+};
+
+SidePool &side_pool() {
+    static SidePool *pool = new SidePool();  // never destroyed
+    return *pool;
+}
+
 PinnedPool &pinned_pool() {
     static PinnedPool *pool = new PinnedPool();  // never destroyed: outlives static teardown
     return *pool;
@@ -119,7 +168,40 @@ struct Ctx {
     }
     ~Ctx() {
         if (in_flight) (void)hipStreamSynchronize(s);
+        if (side.s) {
+            (void)hipStreamSynchronize(side.s);
+            side_pool().put(side);
+        }
         if (hdesc_pageable.empty() && hdesc) pinned_pool().put(hdesc, hdesc_cap);
+    }
+    // A second stream for work that may run beside the main stream's (the
+    // dense Cholesky of a diagonal tile beside the recompression of the tiles
+    // below it).  fork() makes it wait for everything issued on the main
+    // stream so far; join() makes the main stream wait for everything issued
+    // on it.  Staged descriptors stay valid until sync_reset(), which drains
+    // both streams.  Without a side stream both calls are no-ops and the work
+    // simply runs on the main stream.
+    SideStream side;
+    bool side_busy = false;
+    hipStream_t fork() {
+        if (!side.s && !side_pool().get(&side)) return s;
+        if (hipEventRecord(side.from_main, s) != hipSuccess || hipStreamWaitEvent(side.s, side.from_main, 0) != hipSuccess)
+            return s;
+        side_busy = true;
+        return side.s;
+    }
+    tlr_status join() {
+        if (!side_busy) return TLR_OK;
+        TLR_HIP(hipEventRecord(side.from_side, side.s));
+        TLR_HIP(hipStreamWaitEvent(s, side.from_side, 0));
+        return TLR_OK;
+    }
+    tlr_status drain_side() {
+        if (side_busy) {
+            TLR_HIP(hipStreamSynchronize(side.s));
+            side_busy = false;
+        }
+        return TLR_OK;
     }
     Ctx(const Ctx &) = delete;
     Ctx &operator=(const Ctx &) = delete;
@@ -198,6 +280,7 @@ struct Ctx {
     }
     tlr_status sync_reset() {
         TLR_HIP(hipStreamSynchronize(s));
+        TLR_TRY(drain_side());
         in_flight = false;
         ktimer_poll();
         desc_used = 0;
@@ -226,8 +309,10 @@ struct Ctx {
     }
     tlr_status read_status(int *code) {
         int32_t st = 0;
+        TLR_TRY(join());
         TLR_HIP(hipMemcpyAsync(&st, &params()->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         TLR_HIP(hipStreamSynchronize(s));
+        TLR_TRY(drain_side());
         *code = st;
         return TLR_OK;
     }
@@ -918,12 +1003,15 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             std::vector<GemmDesc> gdg{gd(Xd, nb, Yj, nb, c.diag(j), nb, nb, nb, Rj, -1.0, 1.0)};
             TLR_TRY(launch_gemms(c, false, true, gdg));
         }
-        // dense Cholesky of the updated diagonal tile
+        // dense Cholesky of the updated diagonal tile, beside the
+        // recompression of the tiles below (which never reads it); only the
+        // triangular solves at the end of the column need its factor
         {
             std::vector<GemmDesc> pd((size_t)cdiv(nb, 64));
             potrf_tile_descs(c.diag(j), nb, pd.data());
             TLR_PUSH(dpd, c, pd);
-            TLR_LAUNCH(c, potrf_tile(c.diag(j), nb, j, c.params(), dpd, s));
+            TLR_TRY(c.flush());
+            TLR_TRY(potrf_tile(c.diag(j), nb, j, c.params(), dpd, c.fork()));
         }
         // Schur complement of the tiles below, re-compressed once
         std::vector<int> rows;

@@ -86,6 +86,11 @@ def test_launch_timer_host_side():
     resetting and reading with nothing pending, and argument checks."""
     L = B.lib()
     assert L.tlr_kstats_read(None, 4) == -1
+    # restricting the timer to one class and back needs no device
+    L.tlr_kstats_select.restype = ctypes.c_int32
+    L.tlr_kstats_select.argtypes = [ctypes.c_char_p]
+    assert L.tlr_kstats_select(b"k_chol_small") == 0
+    assert L.tlr_kstats_select(None) == 0
     B.kstats_enable(True)
     B.kstats_reset()
     stats = B.kstats()
