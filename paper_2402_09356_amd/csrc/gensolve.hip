@@ -161,9 +161,19 @@ __global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L,
     if (params->status != 0) return;
     for (int b0 = 0; b0 < nb; b0 += 64) {
         const int bs = (nb - b0 < 64) ? nb - b0 : 64;
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int r = e & 63, c = e >> 6;
-            Db[r + 65 * c] = (r < bs && c < bs && r >= c) ? L[(b0 + r) + (int64_t)(b0 + c) * nb] : 0.0;
+        {
+            // sixteen loads a thread, all in flight together
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = tid + 256 * u, r = e & 63, c = e >> 6;
+                v[u] = (r < bs && c < bs && r >= c) ? L[(b0 + r) + (int64_t)(b0 + c) * nb] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = tid + 256 * u, r = e & 63, c = e >> 6;
+                Db[r + 65 * c] = v[u];
+            }
         }
         __syncthreads();
         if (wave == 0) {
@@ -176,25 +186,33 @@ __global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L,
                 else if (lane > r)
                     v -= lr * xr;
             }
-            if (lane < bs) {
-                xb[lane] = v;
-                yv[b0 + lane] = v;
-            }
+            xb[lane] = (lane < bs) ? v : 0.0;  // zero past the block: the row update reads all 64
+            if (lane < bs) yv[b0 + lane] = v;
         }
         __syncthreads();
-        for (int row = b0 + bs + tid; row < nb; row += blockDim.x) {
-            // eight columns at a time so that a batch's loads are in flight together
-            double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            int c = 0;
-            for (; c + 8 <= bs; c += 8) {
-                double lv[8];
+        // rows below the block: four rows a thread and eight columns at a
+        // time, so thirty-two loads are in flight together
+        for (int row0 = b0 + bs + tid; row0 < nb; row0 += 4 * 256) {
+            double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+            for (int c = 0; c < bs; c += 8) {
+                double lv[4][8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) lv[u] = L[row + (int64_t)(b0 + c + u) * nb];
+                for (int k = 0; k < 4; ++k)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) a8[u] += lv[u] * xb[c + u];
+                    for (int u = 0; u < 8; ++u) {
+                        const int row = row0 + 256 * k;
+                        lv[k][u] = (row < nb && c + u < bs) ? L[row + (int64_t)(b0 + c + u) * nb] : 0.0;
+                    }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[k][u & 1] += lv[k][u] * xb[(c + u) & 63];
             }
-            for (; c < bs; ++c) a8[0] += L[row + (int64_t)(b0 + c) * nb] * xb[c];
-            yv[row] -= ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int row = row0 + 256 * k;
+                if (row < nb) yv[row] -= acc[k][0] + acc[k][1];
+            }
         }
         __syncthreads();
     }
@@ -209,6 +227,12 @@ struct GemvDesc {
 };
 
 // y_i <- y_i - U (V^T y_j) for a batch of low-rank tiles (one work-group each).
+// Both products are latency-bound on a single work-group, so every loop keeps
+// a batch of independent loads in flight: y_j is read into registers once,
+// a wave forms two dot products V[:, c]^T y_j at a time, and each thread
+// updates its four rows of y_i from four columns of U at a time.
+constexpr int kGemvRowsPerLane = 16;  // nb <= 1024 in registers; longer tiles loop
+
 __global__ __launch_bounds__(256) void k_lr_gemv(const GemvDesc *__restrict__ descs, int nb,
                                                  const DevParams *params) {
     __shared__ double t[4096];  // rank <= nb <= 4096 (a dense tile has rank nb)
@@ -216,18 +240,65 @@ __global__ __launch_bounds__(256) void k_lr_gemv(const GemvDesc *__restrict__ de
     const int r = *d.r_dev;
     if (r <= 0 || params->status != 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int c = wave; c < r; c += 4) {
-        const double *v = d.V + (int64_t)c * nb;
-        double acc = 0.0;
-        for (int q = lane; q < nb; q += 64) acc += v[q] * d.yj[q];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) t[c] = acc;
+    for (int q0 = 0; q0 < nb; q0 += 64 * kGemvRowsPerLane) {
+        double yj[kGemvRowsPerLane];
+#pragma unroll
+        for (int u = 0; u < kGemvRowsPerLane; ++u) {
+            const int q = q0 + lane + 64 * u;
+            yj[u] = (q < nb) ? d.yj[q] : 0.0;
+        }
+        for (int c = wave; c < r; c += 8) {
+            const int c2 = c + 4;
+            const double *v1 = d.V + (int64_t)c * nb;
+            const double *v2 = d.V + (int64_t)(c2 < r ? c2 : c) * nb;
+            double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+            for (int u = 0; u < kGemvRowsPerLane; ++u) {
+                const int q = q0 + lane + 64 * u;
+                const double w1 = (q < nb) ? v1[q] : 0.0;
+                const double w2 = (q < nb) ? v2[q] : 0.0;
+                a1 += w1 * yj[u];
+                a2 += w2 * yj[u];
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                a1 += __shfl_xor(a1, off, 64);
+                a2 += __shfl_xor(a2, off, 64);
+            }
+            if (lane == 0) {
+                t[c] = (q0 == 0) ? a1 : t[c] + a1;
+                if (c2 < r) t[c2] = (q0 == 0) ? a2 : t[c2] + a2;
+            }
+        }
     }
     __syncthreads();
-    for (int row = tid; row < nb; row += blockDim.x) {
-        double acc = 0.0;
-        for (int c = 0; c < r; ++c) acc += d.U[row + (int64_t)c * nb] * t[c];
-        d.yi[row] -= acc;
+    for (int row0 = tid; row0 < nb; row0 += 4 * 256) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int c = 0;
+        for (; c + 4 <= r; c += 4) {
+            double uv[4][4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int row = row0 + 256 * k;
+                    uv[k][w] = (row < nb) ? d.U[row + (int64_t)(c + w) * nb] : 0.0;
+                }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) acc[k] += uv[k][w] * t[c + w];
+        }
+        for (; c < r; ++c)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int row = row0 + 256 * k;
+                if (row < nb) acc[k] += d.U[row + (int64_t)c * nb] * t[c];
+            }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int row = row0 + 256 * k;
+            if (row < nb) d.yi[row] -= acc[k];
+        }
     }
 }
 
