@@ -57,55 +57,114 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
+// One wave factors diagonal tile b in registers (lane r holds row r); sets
+// *s_fail on failure.  Called by wave 0 only.
+__device__ __forceinline__ void diag_tile(double *TS, int b, int k, double defl, double *inv, int *s_fail) {
+    const int lane = threadIdx.x & 63;
+    double *D = TS + (tri(b) + b) * kTW;
+    const int r = lane & 15;
+    double a[kT];
+#pragma unroll
+    for (int q = 0; q < kT; ++q) a[q] = D[r + kTP * q];
+    const double dstart = D[r + kTP * r];  // this row's diagonal entry before the tile's steps
+    int fail = 0;
+#pragma unroll
+    for (int c = 0; c < kT; ++c) {
+        const double piv = readlane_d(a[c], c);
+        const int gc = kT * b + c;
+        // the cases resolve by selects, off the pivot's critical path:
+        // padding (1), failure or dead direction (0), else sqrt(piv)
+        const double ivr = rsqrt(piv);
+        const bool pad = gc >= k;
+        const bool bad = !isfinite(piv) || (defl == 0.0 && !(piv > kPivotLoss * readlane_d(dstart, c)));
+        const bool zero = bad || (defl > 0.0 && piv <= defl);
+        if (bad && !pad && !fail) fail = gc + 1;
+        const double iv = pad ? 1.0 : (zero ? 0.0 : ivr);
+        const double lcc = pad ? 1.0 : (zero ? 0.0 : piv * ivr);
+        const double lrc = (r == c) ? lcc : ((r > c) ? a[c] * iv : 0.0);
+        a[c] = lrc;
+        // entry (q, c) of the new column sits in lane q of every row
+        double lq[kT];
+#pragma unroll
+        for (int q = c + 1; q < kT; ++q) lq[q] = row_bcast_at(lrc, q);
+#pragma unroll
+        for (int q = c + 1; q < kT; ++q) a[q] -= lrc * lq[q];
+        if (lane == c) inv[c] = iv;
+    }
+    if (lane < kT) {
+#pragma unroll
+        for (int q = 0; q < kT; ++q) D[r + kTP * q] = (q <= r) ? a[q] : 0.0;
+    }
+    if (lane == 0 && fail) *s_fail = fail;
+}
+
+// Trailing tiles t0, t0 + step, ... of step b (t numbers the tiles (i, j),
+// b < j <= i, row by row from (b+1, b+1)): A_ij -= L_ib L_jb^T, two tiles at a
+// time so that their operand reads and MFMA chains overlap.
+__device__ __forceinline__ void trail_tiles(double *TS, int b, int count, int t0, int step) {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    auto tile_of = [&](int t, int &i, int &j) {
+        int ip = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while (tri(ip + 1) <= t) ++ip;
+        while (tri(ip) > t) --ip;
+        i = b + 1 + ip;
+        j = b + 1 + (t - tri(ip));
+    };
+#pragma unroll 1
+    for (int t = t0; t < count; t += 2 * step) {
+        const bool two = t + step < count;
+        int i1, j1, i2, j2;
+        tile_of(t, i1, j1);
+        tile_of(two ? t + step : t, i2, j2);
+        double *C1 = TS + (tri(i1) + j1) * kTW;
+        double *C2 = TS + (tri(i2) + j2) * kTW;
+        const double *L1i = TS + (tri(i1) + b) * kTW, *L1j = TS + (tri(j1) + b) * kTW;
+        const double *L2i = TS + (tri(i2) + b) * kTW, *L2j = TS + (tri(j2) + b) * kTW;
+        v4d acc1, acc2;
+        double a1[4], b1[4], a2[4], b2[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc1[q] = C1[(lg + 4 * q) + kTP * li];
+            acc2[q] = C2[(lg + 4 * q) + kTP * li];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            a1[s] = -L1i[li + kTP * (4 * s + lg)];
+            b1[s] = L1j[li + kTP * (4 * s + lg)];
+            a2[s] = -L2i[li + kTP * (4 * s + lg)];
+            b2[s] = L2j[li + kTP * (4 * s + lg)];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], b2[s], acc2, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) C1[(lg + 4 * q) + kTP * li] = acc1[q];
+        if (two) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) C2[(lg + 4 * q) + kTP * li] = acc2[q];
+        }
+    }
+}
+
 // Factor the tiles in TS (tile rows T); returns the failing column + 1, or 0.
+// Look-ahead: during the trailing update of step b, wave 0 updates tile
+// (b+1, b+1) first and factors it at once, while the other waves update the
+// rest, so each diagonal factorisation (a chain of sixteen dependent pivots)
+// overlaps the previous step's updates.
 template <bool LDS>
 __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, int *s_fail) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    constexpr int kW = kThreads / 64;
+    if (wave == 0) diag_tile(TS, 0, k, defl, inv, s_fail);
+    __syncthreads();
+    if (*s_fail) return *s_fail;
 #pragma unroll 1
-    for (int b = 0; b < T; ++b) {
-        // 1. diagonal tile
-        if (wave == 0) {
-            double *D = TS + (tri(b) + b) * kTW;
-            const int r = lane & 15;
-            double a[kT];
-#pragma unroll
-            for (int q = 0; q < kT; ++q) a[q] = D[r + kTP * q];
-            const double dstart = D[r + kTP * r];  // this row's diagonal entry before the tile's steps
-            int fail = 0;
-#pragma unroll
-            for (int c = 0; c < kT; ++c) {
-                const double piv = readlane_d(a[c], c);
-                const int gc = kT * b + c;
-                // the cases resolve by selects, off the pivot's critical path:
-                // padding (1), failure or dead direction (0), else sqrt(piv)
-                const double ivr = rsqrt(piv);
-                const bool pad = gc >= k;
-                const bool bad = !isfinite(piv) || (defl == 0.0 && !(piv > kPivotLoss * readlane_d(dstart, c)));
-                const bool zero = bad || (defl > 0.0 && piv <= defl);
-                if (bad && !pad && !fail) fail = gc + 1;
-                const double iv = pad ? 1.0 : (zero ? 0.0 : ivr);
-                const double lcc = pad ? 1.0 : (zero ? 0.0 : piv * ivr);
-                const double lrc = (r == c) ? lcc : ((r > c) ? a[c] * iv : 0.0);
-                a[c] = lrc;
-                // entry (q, c) of the new column sits in lane q of every row
-                double lq[kT];
-#pragma unroll
-                for (int q = c + 1; q < kT; ++q) lq[q] = row_bcast_at(lrc, q);
-#pragma unroll
-                for (int q = c + 1; q < kT; ++q) a[q] -= lrc * lq[q];
-                if (lane == c) inv[c] = iv;
-            }
-            if (lane < kT) {
-#pragma unroll
-                for (int q = 0; q < kT; ++q) D[r + kTP * q] = (q <= r) ? a[q] : 0.0;
-            }
-            if (lane == 0 && fail) *s_fail = fail;
-        }
-        __syncthreads();
-        if (*s_fail) return *s_fail;
+    for (int b = 0; b + 1 < T; ++b) {
         const int n = T - b - 1;
-        if (n == 0) break;
-        // 2. panel rows: x L_bb^T = a
+        // panel rows: x L_bb^T = a
         const double *D = TS + (tri(b) + b) * kTW;
 #pragma unroll 1
         for (int rr = tid; rr < kT * n; rr += kThreads) {
@@ -127,56 +186,16 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
             for (int q = 0; q < kT; ++q) P[r + kTP * q] = a[q];
         }
         __syncthreads();
-        // 3. trailing tiles
         const int count = tri(n);
-        const int li = lane & 15, lg = lane >> 4;
-        // two tiles a wave at a time: their operand reads and MFMA chains
-        // are independent and overlap
-        auto tile_of = [&](int t, int &i, int &j) {
-            int ip = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-            while (tri(ip + 1) <= t) ++ip;
-            while (tri(ip) > t) --ip;
-            i = b + 1 + ip;
-            j = b + 1 + (t - tri(ip));
-        };
-        constexpr int kW = kThreads / 64;
-#pragma unroll 1
-        for (int t = wave; t < count; t += 2 * kW) {
-            const bool two = t + kW < count;
-            int i1, j1, i2, j2;
-            tile_of(t, i1, j1);
-            tile_of(two ? t + kW : t, i2, j2);
-            double *C1 = TS + (tri(i1) + j1) * kTW;
-            double *C2 = TS + (tri(i2) + j2) * kTW;
-            const double *L1i = TS + (tri(i1) + b) * kTW, *L1j = TS + (tri(j1) + b) * kTW;
-            const double *L2i = TS + (tri(i2) + b) * kTW, *L2j = TS + (tri(j2) + b) * kTW;
-            v4d acc1, acc2;
-            double a1[4], b1[4], a2[4], b2[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc1[q] = C1[(lg + 4 * q) + kTP * li];
-                acc2[q] = C2[(lg + 4 * q) + kTP * li];
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                a1[s] = -L1i[li + kTP * (4 * s + lg)];
-                b1[s] = L1j[li + kTP * (4 * s + lg)];
-                a2[s] = -L2i[li + kTP * (4 * s + lg)];
-                b2[s] = L2j[li + kTP * (4 * s + lg)];
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], acc1, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], b2[s], acc2, 0, 0, 0);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) C1[(lg + 4 * q) + kTP * li] = acc1[q];
-            if (two) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) C2[(lg + 4 * q) + kTP * li] = acc2[q];
-            }
+        if (wave == 0) {
+            trail_tiles(TS, b, 1, 0, 1);  // tile (b+1, b+1)
+            __threadfence_block();        // its update, written across lanes, is read back by rows
+            diag_tile(TS, b + 1, k, defl, inv, s_fail);
+        } else {
+            trail_tiles(TS, b, count, wave, kW - 1);
         }
         __syncthreads();
+        if (*s_fail) return *s_fail;
     }
     return 0;
 }

@@ -235,19 +235,22 @@ tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int
             flops += 2.0 * M * N * K;
             bytes += 8.0 * (M * K + K * N + M * N * (g.beta != 0.0 ? 2.0 : 1.0));
         }
-    // tall products (many rows of C) with a transposed left factor or a
-    // right factor wider than 64 go to the LDS-staged kernel, which reads
+    // tall products (many rows of C) go to the LDS-staged kernel, which reads
     // both operands along their contiguous index and needs no final
-    // reduction; the rest keep the K-split kernel, which spreads a long K
-    // over four waves (Gram matrices, narrow sketches)
+    // reduction: 64 x 64 blocks for a right factor of 33..64 columns, else
+    // 64 x 32; short ones keep the K-split kernel, which spreads a long K over
+    // four waves (Gram matrices, small sketches)
     const int row_blocks = (int)cdiv(max_m, 64);
-    if (!trans_b && (trans_a || max_n > 64) && max_m >= kTallM && (int64_t)row_blocks * count >= kTallBlocks) {
+    if (!trans_b && max_m >= kTallM && (int64_t)row_blocks * count >= kTallBlocks) {
         static const int cls_t = ktimer_class("k_gemm_lds<T,N>"), cls_w = ktimer_class("k_gemm_lds<N,N>");
         KTimer kt(trans_a ? cls_t : cls_w, s, flops, bytes, exact);
-        if (trans_a && max_n > 32) {
+        if (max_n > 32 && (trans_a || max_n <= 64)) {
             const int tn = (int)cdiv(max_n, 64);
             const dim3 grid((unsigned)(row_blocks * tn), (unsigned)count);
-            hipLaunchKernelGGL((k_gemm_lds<true, false, 64, 64>), grid, dim3(256), 0, s, d_descs, tn);
+            if (trans_a)
+                hipLaunchKernelGGL((k_gemm_lds<true, false, 64, 64>), grid, dim3(256), 0, s, d_descs, tn);
+            else
+                hipLaunchKernelGGL((k_gemm_lds<false, false, 64, 64>), grid, dim3(256), 0, s, d_descs, tn);
         } else {
             const int tn = (int)cdiv(max_n, 32);
             const dim3 grid((unsigned)(row_blocks * tn), (unsigned)count);
