@@ -483,6 +483,10 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
         }
         __syncthreads();
         const double bta = bet[c];
+        // row blocks wholly above row c are finished: the reflector is zero
+        // there, so they are skipped (one uniform branch per block; the terms
+        // left out are exact zeros, so every sum keeps its bits)
+        const int rb0 = c >> 4;
         double vr[RPS];
 #pragma unroll
         for (int rr = 0; rr < RPS; ++rr) vr[rr] = vsh[sl + 16 * rr];
@@ -492,24 +496,32 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
         for (int cc = 0; cc < CPG; ++cc) {
             const int p = grp + G * cc;
             act[cc] = p < k && pst[p] == kNever;
-            double t = 0.0;
-#pragma unroll
-            for (int rr = 0; rr < RPS; ++rr) t += vr[rr] * a[cc][rr];
-            w[cc] = act[cc] ? t : 0.0;
+            w[cc] = 0.0;
         }
 #pragma unroll
-        for (int cc = 0; cc < CPG; ++cc) w[cc] = red16(w[cc]) * bta;
+        for (int rr = 0; rr < RPS; ++rr) {
+            if (rr < rb0) continue;
 #pragma unroll
-        for (int cc = 0; cc < CPG; ++cc) {
-            double n2 = 0.0;
+            for (int cc = 0; cc < CPG; ++cc) w[cc] += vr[rr] * a[cc][rr];
+        }
 #pragma unroll
-            for (int rr = 0; rr < RPS; ++rr) {
-                const int i = sl + 16 * rr;
+        for (int cc = 0; cc < CPG; ++cc) w[cc] = red16(act[cc] ? w[cc] : 0.0) * bta;
+        double n2[CPG];
+#pragma unroll
+        for (int cc = 0; cc < CPG; ++cc) n2[cc] = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < RPS; ++rr) {
+            if (rr < rb0) continue;
+            const int i = sl + 16 * rr;
+            const bool below = i > c && i < k;
+#pragma unroll
+            for (int cc = 0; cc < CPG; ++cc) {
                 a[cc][rr] -= w[cc] * vr[rr];
-                if (i > c && i < k) n2 += a[cc][rr] * a[cc][rr];
+                if (below) n2[cc] += a[cc][rr] * a[cc][rr];
             }
-            w[cc] = n2;
         }
+#pragma unroll
+        for (int cc = 0; cc < CPG; ++cc) w[cc] = n2[cc];
 #pragma unroll
         for (int cc = 0; cc < CPG; ++cc) {
             const double n2 = red16(w[cc]);
