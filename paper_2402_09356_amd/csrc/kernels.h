@@ -85,9 +85,13 @@ tlr_status copy_batched(const CopyDesc *d_descs, int count, int64_t max_words, h
 tlr_status identity_batched(double *const *d_ptrs, int count, int nb, hipStream_t s);
 // B_t <- L^-1 B_t for `count` right-hand-side panels (nb x cols_t, ld nb),
 // L lower (nb x nb).  descs: A = L (shared), Y = B_t, k = cols_t.
-// d_gemm / h_gemm: room for count * ceil(nb/64) descriptors.
+// d_gemm / h_gemm: room for count * ceil(nb/64) descriptors; h_gemm ==
+// nullptr means the caller has already put them at d_gemm (see below).
 tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, const SmallDesc *h_descs,
                            int count, int max_cols, GemmDesc *d_gemm, GemmDesc *h_gemm, hipStream_t s);
+// The GEMM descriptors trsm_left_lower uses (ceil(nb/64) * count entries,
+// block major), for a caller that uploads them itself.
+void trsm_left_lower_descs(const double *L, int nb, const SmallDesc *h_descs, int count, GemmDesc *h_gemm);
 
 // Matern tile generation.
 struct GenDesc {

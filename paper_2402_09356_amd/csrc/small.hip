@@ -837,9 +837,7 @@ tlr_status copy_batched(const CopyDesc *d_descs, int count, int64_t max_words, h
     return TLR_OK;
 }
 
-tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, const SmallDesc *h_descs,
-                           int count, int max_cols, GemmDesc *d_gemm, GemmDesc *h_gemm, hipStream_t s) {
-    if (count <= 0 || max_cols <= 0) return TLR_OK;
+void trsm_left_lower_descs(const double *L, int nb, const SmallDesc *h_descs, int count, GemmDesc *h_gemm) {
     const int nblk = (int)cdiv(nb, 64);
     // block b, panel t: Y_t[b0+bs:, :] -= L[b0+bs:, b0:b0+bs] * Y_t[b0:b0+bs, :]
     for (int b = 0; b < nblk; ++b) {
@@ -863,7 +861,16 @@ tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, co
             h_gemm[(int64_t)b * count + t] = o;
         }
     }
-    TLR_HIP(hipMemcpyAsync(d_gemm, h_gemm, sizeof(GemmDesc) * count * nblk, hipMemcpyHostToDevice, s));
+}
+
+tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, const SmallDesc *h_descs,
+                           int count, int max_cols, GemmDesc *d_gemm, GemmDesc *h_gemm, hipStream_t s) {
+    if (count <= 0 || max_cols <= 0) return TLR_OK;
+    const int nblk = (int)cdiv(nb, 64);
+    if (h_gemm) {  // else the caller has put the descriptors on the device
+        trsm_left_lower_descs(L, nb, h_descs, count, h_gemm);
+        TLR_HIP(hipMemcpyAsync(d_gemm, h_gemm, sizeof(GemmDesc) * count * nblk, hipMemcpyHostToDevice, s));
+    }
     for (int b = 0; b < nblk; ++b) {
         const int b0 = b * 64, bs = (nb - b0 < 64) ? nb - b0 : 64;
         const int rest = nb - b0 - bs;

@@ -292,6 +292,7 @@ struct Ctx {
     struct StatRead {
         std::vector<int32_t> raw;
         int64_t t0 = 0;
+        int32_t status = 0;  // the device status word, read in the same copy batch
     };
     template <class JobT>
     tlr_status read_stats(const std::vector<JobT> &jobs, StatRead &sr) {
@@ -305,6 +306,7 @@ struct Ctx {
         sr.t0 = lo;
         sr.raw.assign((size_t)(hi - lo + 1) * 4, 0);
         TLR_HIP(hipMemcpyAsync(sr.raw.data(), tstat(lo), sizeof(int32_t) * sr.raw.size(), hipMemcpyDeviceToHost, s));
+        TLR_HIP(hipMemcpyAsync(&sr.status, &params()->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         return TLR_OK;
     }
     tlr_status read_status(int *code) {
@@ -960,6 +962,9 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
         for (int j = 0; j < i; ++j)
             if (r[(size_t)i * nt + j] < 0) return TLR_OK;  // overflow recorded by compress
     std::vector<GemmDesc> hg((size_t)nt * 64 + 64);
+    // a failure recorded on the device (a pivot lost, an arena overflow) is
+    // seen at the next status read-back; the factorisation then stops
+    bool failed = false;
     for (int j = 0; j < nt; ++j) {
         c.arena_used = 0;
         int Rj = 0;
@@ -1024,7 +1029,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                 const int kfull = std::min(tile_rows(p, i), tile_rows(p, j));
                 kk[i] = ladder_k(p, r[(size_t)i * nt + j] + p->pover, kfull);
             }
-            while (!todo.empty()) {
+            while (!todo.empty() && !failed) {
                 std::vector<int> retry;
                 size_t pos = 0;
                 while (pos < todo.size()) {
@@ -1123,6 +1128,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                     Ctx::StatRead sr;
                     TLR_TRY(c.read_stats(jobs, sr));
                     TLR_TRY(c.sync_reset());
+                    if (!jobs.empty() && sr.status != 0) failed = true;
                     std::vector<int32_t> st(4 * jobs.size());
                     for (size_t q = 0; q < jobs.size(); ++q)
                         std::memcpy(&st[4 * q], &sr.raw[(size_t)(tile_index(jobs[q].i, jobs[q].j) - sr.t0) * 4],
@@ -1174,9 +1180,9 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             }
             c.arena_used = mark;
         }
-        int code = 0;
-        TLR_TRY(c.read_status(&code));
-        if (code != 0) break;
+        if (failed) break;
+        // the triangular solves need the diagonal factor from the side stream
+        TLR_TRY(c.join());
         // L_ij = U_ij (L_jj^-1 V_ij)^T
         std::vector<SmallDesc> sd;
         int maxc = 0;
@@ -1193,15 +1199,18 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
         if (!sd.empty()) {
             TLR_PUSH(dsd, c, sd);
             const size_t nblk = (size_t)cdiv(nb, 64);
-            const size_t need = align_up(sizeof(GemmDesc) * sd.size() * nblk, 256);
-            if (c.desc_used + need > p->desc_bytes) return TLR_E_NOMEM;
-            GemmDesc *dg = reinterpret_cast<GemmDesc *>(c.ws + p->off_desc + c.desc_used);
             if (hg.size() < sd.size() * nblk) hg.resize(sd.size() * nblk);
-            c.desc_used += need;
-            TLR_LAUNCH(c, trsm_left_lower(c.diag(j), nb, dsd, sd.data(), (int)sd.size(), maxc, dg, hg.data(), s));
+            trsm_left_lower_descs(c.diag(j), nb, sd.data(), (int)sd.size(), hg.data());
+            GemmDesc *dg = c.push(hg.data(), sd.size() * nblk);
+            if (!dg) return TLR_E_NOMEM;
+            TLR_LAUNCH(c, trsm_left_lower(c.diag(j), nb, dsd, sd.data(), (int)sd.size(), maxc, dg, nullptr, s));
         }
-        TLR_TRY(c.sync_reset());
+        // no wait here: the next column's first launches queue behind these
+        // (its status read-back drains both streams); the descriptor area is
+        // recycled early only when it runs half full
+        if (c.desc_used > p->desc_bytes / 2) TLR_TRY(c.sync_reset());
     }
+    TLR_TRY(c.sync_reset());
     TLR_TRY(c.store_dense());
     TLR_HIP(hipMemcpyAsync(c.rL(), r.data(), sizeof(int32_t) * r.size(), hipMemcpyHostToDevice, s));
     TLR_HIP(hipStreamSynchronize(s));
