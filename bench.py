@@ -175,7 +175,7 @@ def main():
     warm_stats = B.kstats()
     B.kstats_enable(False)
     timed_class = warm_stats[0]["name"] if warm_stats and warm_stats[0]["launches"] > 0 else None
-    for k in warm_stats[:12]:
+    for k in warm_stats[:16]:
         print(f"# warm-up {k['name']:20s} launches {k['launches']:7d}  total {k['total_ms']:10.2f} ms  "
               f"avg {1e3 * k['total_ms'] / max(k['launches'], 1):9.2f} us", file=sys.stderr)
     lat = [0.0] * args.steps

@@ -871,11 +871,24 @@ tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, co
         trsm_left_lower_descs(L, nb, h_descs, count, h_gemm);
         TLR_HIP(hipMemcpyAsync(d_gemm, h_gemm, sizeof(GemmDesc) * count * nblk, hipMemcpyHostToDevice, s));
     }
+    static const int cls = ktimer_class("k_trsm_block");
+    double cols_sum = 0.0;
+    bool exact = h_descs != nullptr;
+    if (exact)
+        for (int t = 0; t < count; ++t) {
+            if (h_descs[t].k_dev) exact = false;
+            cols_sum += h_descs[t].k;
+        }
     for (int b = 0; b < nblk; ++b) {
         const int b0 = b * 64, bs = (nb - b0 < 64) ? nb - b0 : 64;
         const int rest = nb - b0 - bs;
-        hipLaunchKernelGGL(k_trsm_block, dim3((unsigned)cdiv(max_cols, 64), count), dim3(64), 0, s, L, nb,
-                           b0, bs, d_descs);
+        {
+            const double d = bs;
+            // bs^2 flops per right-hand side; the block of L once, each column read and written once
+            KTimer kt(cls, s, d * d * cols_sum, 8.0 * (d * (d + 1.0) / 2.0 + 2.0 * d * cols_sum), exact);
+            hipLaunchKernelGGL(k_trsm_block, dim3((unsigned)cdiv(max_cols, 64), count), dim3(64), 0, s, L, nb,
+                               b0, bs, d_descs);
+        }
         if (rest > 0)
             TLR_TRY(gemm_batched(false, false, d_gemm + (int64_t)b * count, count, rest, max_cols, s));
     }
