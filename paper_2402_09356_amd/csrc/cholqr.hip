@@ -304,6 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_small(const SmallDesc *__rest
 // solves against the diagonal block one row a lane.  A zero diagonal of R
 // (dead direction) gives a zero column.
 constexpr int kTrsmLdsK = 192;
+constexpr int kBigBatchGroups = 2048;  // eight per compute unit
 constexpr int kYP = 65;  // LDS pitch of a column of the 64-row block
 
 // kcap: the launch's largest k up to 192, padded to 16 (sizes the LDS).
@@ -423,15 +424,16 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restr
     }
 }
 
-// The same for k > 192, with Y read from and written to global memory (the
-// earlier blocks' X is read back from Y).
-__global__ __launch_bounds__(kThreads) void k_trsm_rows_wide(const SmallDesc *__restrict__ descs) {
+// The same with Y read from and written to global memory (the earlier
+// blocks' X is read back from Y), for every k above k_lo: k > 192, or all k
+// in batches too large for one LDS-bound work-group per compute unit.
+__global__ __launch_bounds__(kThreads) void k_trsm_rows_wide(const SmallDesc *__restrict__ descs, int k_lo) {
     extern __shared__ double Rb[];
     const SmallDesc d = descs[blockIdx.y];
     const int k = d.k_dev ? *d.k_dev : d.k;
     const int m = d.m;
     const int r0 = blockIdx.x * 64;
-    if (k <= kTrsmLdsK || r0 >= m) return;
+    if (k <= k_lo || r0 >= m) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int rowbase = r0 + kT * wave;
@@ -647,17 +649,27 @@ tlr_status trsm_rows(const SmallDesc *d_descs, int count, int max_m, int max_k, 
             }
         }
     const dim3 grid((unsigned)cdiv(max_m, 64), (unsigned)count);
-    {
+    // The LDS-resident kernel holds one or two work-groups per compute unit;
+    // it pays off while the batch is a few work-groups per unit (a column of
+    // the factorisation, at most 99 panels of 15 row blocks).  Larger batches
+    // (a compression wave) keep every unit busy with the global-memory kernel.
+    const bool big = (int64_t)grid.x * grid.y > kBigBatchGroups;
+    int k_lo = kTrsmLdsK;
+    if (big) {
+        k_lo = 0;
+        flops_w += flops;
+        bytes_w += bytes;
+    } else {
         const int kcap = (std::min(max_k, kTrsmLdsK) + kT - 1) / kT * kT;
         const size_t lds = sizeof(double) * ((size_t)kYP * kcap + (size_t)kcap * kTP);
         KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
         hipLaunchKernelGGL(k_trsm_rows, grid, dim3(kThreads), lds, s, d_descs, kcap);
     }
-    if (max_k > kTrsmLdsK) {
+    if (max_k > k_lo) {
         const int kp = (max_k + kT - 1) / kT * kT;
         const size_t lds = sizeof(double) * (size_t)kp * kTP;
         KTimer kt(cls_w, s, flops_w, bytes_w, h_descs != nullptr);
-        hipLaunchKernelGGL(k_trsm_rows_wide, grid, dim3(kThreads), lds, s, d_descs);
+        hipLaunchKernelGGL(k_trsm_rows_wide, grid, dim3(kThreads), lds, s, d_descs, k_lo);
     }
     TLR_HIP(hipGetLastError());
     return TLR_OK;
