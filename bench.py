@@ -94,6 +94,7 @@ def roofline(stats, workload: str, warm_stats=None):
                 "traffic": None, "avg_launch_us": 1e3 * top["total_ms"] / max(top["launches"], 1),
                 "launches": top["launches"], "note": "work of this kernel is decided on the device"}
     sec = top["exact_ms"] * 1e-3
+    note = None
     t_flops = top["flops"] / (PEAK_FP64_TFLOPS * 1e12)
     t_bytes = top["bytes"] / (PEAK_HBM_GBS * 1e9)
     per = top["exact_launches"]
@@ -102,8 +103,11 @@ def roofline(stats, workload: str, warm_stats=None):
     else:
         bound = "alu" if top["name"] in VALU_KERNELS else "mfma"
         achieved, peak, unit = top["flops"] / sec / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
+    if achieved / peak < 0.05 and top["flops"] / sec / 1e12 / PEAK_FP64_TFLOPS < 0.05:
+        note = ("latency-bound: neither HBM nor FP64 throughput limits it; its time is the dependent chain "
+                "of the largest problem in each batched launch")
     return {"kernel": top["name"], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": measured_traffic(top["name"], workload),
+            "frac": achieved / peak, "traffic": measured_traffic(top["name"], workload), "note": note,
             "avg_launch_us": 1e3 * top["total_ms"] / max(top["launches"], 1), "launches": top["launches"],
             "exact_launches": per, "exact_avg_launch_us": 1e3 * top["exact_ms"] / per,
             "algorithmic_bytes_per_launch": top["bytes"] / per, "algorithmic_flops_per_launch": top["flops"] / per,
@@ -260,6 +264,10 @@ def main():
         "rank_sum": st["rank_sum"],
         "all_finite": bool(np.all(np.isfinite(lls))),
         "roofline": roofline(stats, workload, warm_stats),
+        # the same record for the busiest matrix-core GEMM class, from the
+        # warm-up steps (where every class is timed): context for the above
+        "roofline_gemm": next((roofline([w], workload, warm_stats) for w in warm_stats
+                               if w["name"].startswith("k_gemm") and w["exact_launches"] > 0), None),
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
