@@ -34,18 +34,34 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
+# kernel templates whose arguments name distinct timer classes; any other
+# template's arguments are dropped (k_gen_tiles<0> -> k_gen_tiles)
+_KEEP_ARGS = ("k_gemm_f64", "k_gemm_lds", "k_qrcp_regs")
+
+
 def short_name(kernel: str) -> str:
-    """Kernel class name as the launch timer reports it (mangled or
-    demangled symbol in, e.g. "k_gemm_f64<T,N>" out)."""
-    m = re.search(r"k_gemm_f64ILb(\d)ELb(\d)E", kernel)
+    """Kernel class name as the launch timer reports it, from a mangled or
+    demangled symbol: "k_gemm_f64<T,N>", "k_gemm_lds<N,N,64,32>",
+    "k_qrcp_regs<8,6,12>", "k_chol_small", ..."""
+    m = re.search(r"(k_[a-z][a-z_0-9]*?)I((?:L[bi]\d+E)+)E", kernel)  # mangled template
     if m:
-        ta, tb = m.group(1) == "1", m.group(2) == "1"
-        return "k_gemm_f64<%s,%s>" % ("T" if ta else "N", "T" if tb else "N")
-    m = re.search(r"k_gemm_f64<(true|false), ?(true|false)>", kernel)
-    if m:
-        return "k_gemm_f64<%s,%s>" % ("T" if m.group(1) == "true" else "N", "T" if m.group(2) == "true" else "N")
-    m = re.search(r"(k_[a-z][a-z_0-9]*)", kernel)
-    return m.group(1) if m else kernel.split("(")[0][:60]
+        base = m.group(1)
+        args = re.findall(r"L([bi])(\d+)E", m.group(2))
+        vals = [("T" if v == "1" else "N") if t == "b" else v for t, v in args]
+    else:
+        m = re.search(r"(k_[a-z][a-z_0-9]*)<([^>]*)>", kernel)  # demangled template
+        if m:
+            base = m.group(1)
+            vals = []
+            for a in m.group(2).split(","):
+                a = a.strip()
+                vals.append({"true": "T", "false": "N"}.get(a, a))
+        else:
+            m = re.search(r"(k_[a-z][a-z_0-9]*)", kernel)
+            return m.group(1) if m else kernel.split("(")[0][:60]
+    if base not in _KEEP_ARGS:
+        return base
+    return "%s<%s>" % (base, ",".join(vals))
 
 
 def read_counter(dirpath: str, counter: str):
