@@ -234,7 +234,7 @@ def main():
     ap.add_argument("--maxrank", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-7)
     # each fit waits this long between a result and its next proposal; with 32
-    # fits this keeps the offered load near 0.8 of the measured capacity
+    # fits this offers about two thirds of the saturated capacity
     ap.add_argument("--think-ms", type=float, default=3500.0)
     ap.add_argument("--evals-per-fit", type=int, default=12)
     args = ap.parse_args()
