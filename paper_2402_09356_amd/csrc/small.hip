@@ -336,56 +336,20 @@ __device__ void qrcp_trunc(double *M, int ld, int k, double tol2, double *cn, do
 // vector is kept in V (k x k scratch, column c).  Same arithmetic as
 // qrcp_trunc (pivot = largest remaining norm, smallest index on ties; stop
 // when the remaining Frobenius norm is <= tol), so Y = B^T comes straight from
-// the registers and Q1 is accumulated in registers from V.
-// (sum, largest value with the smallest index on ties) over the wave: a DPP
-// butterfly inside each row of 16 lanes, then the four rows by readlane.
-template <int CTRL>
-__device__ __forceinline__ void pivot_step(double &rem, double &best, int &bj) {
-    rem += dpp_d<CTRL>(rem);
-    const double ob = dpp_d<CTRL>(best);
-    const int oj = dpp_i<CTRL>(bj);
-    if (ob > best || (ob == best && oj < bj)) {
-        best = ob;
-        bj = oj;
-    }
-}
-
-__device__ __forceinline__ void pivot_reduce(double &rem, double &best, int &bj) {
-    pivot_step<kDppXor1>(rem, best, bj);
-    pivot_step<kDppXor2>(rem, best, bj);
-    pivot_step<kDppHalfMirror>(rem, best, bj);
-    pivot_step<kDppMirror>(rem, best, bj);
-    double rs[4], bs[4];
-    int js[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        rs[q] = readlane_d(rem, 16 * q);
-        bs[q] = readlane_d(best, 16 * q);
-        js[q] = __builtin_amdgcn_readlane(bj, 16 * q);
-    }
-    rem = (rs[0] + rs[1]) + (rs[2] + rs[3]);
-    best = bs[0];
-    bj = js[0];
-#pragma unroll
-    for (int q = 1; q < 4; ++q)
-        if (bs[q] > best || (bs[q] == best && js[q] < bj)) {
-            best = bs[q];
-            bj = js[q];
-        }
-}
-
+// the registers and Q1 is accumulated in registers from V.  The column norms
+// stay in registers too: each step's pivot search reduces them within the
+// wave and across waves through LDS, and a step needs two barriers.
 template <int NW, int CPG, int RPS>
 __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restrict__ descs, double tol,
                                                         int min_tail, int k_full, int rank_cap, DevParams *params,
                                                         int kmin) {
     constexpr int G = 4 * NW, KC = G * CPG, KR = 16 * RPS, NT = NW * 64;
     constexpr int kNever = 1 << 30;
-    __shared__ double cn[KC];
     __shared__ int pst[KC];  // step at which the column was pivoted (kNever: not yet)
     __shared__ double vsh[KR];
     __shared__ double bet[KR];
-    __shared__ double redv[2 * NW];
-    __shared__ int redi[NW];
+    __shared__ double redv[2][2 * NW];  // per wave: trailing norm, best norm; by step parity
+    __shared__ int redi[2][NW];
     const SmallDesc d = descs[blockIdx.x];
     const int k = d.k_dev ? *d.k_dev : d.k;
     if (k <= 0 && kmin <= 1) {
@@ -401,6 +365,10 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
     const double tol2 = tol * tol;
     double *__restrict__ V = d.R;
     double a[CPG][RPS];
+    // per column of the group: squared norm of its rows below the current
+    // step (the same in all 16 lanes), and whether it is still unpivoted
+    double cnr[CPG];
+    bool act[CPG];
 #pragma unroll
     for (int cc = 0; cc < CPG; ++cc) {
         const int p = grp + G * cc;
@@ -411,25 +379,52 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
             a[cc][rr] = (p < k && i < k) ? d.A[i + (int64_t)p * d.lda] : 0.0;
             n2 += a[cc][rr] * a[cc][rr];
         }
-        n2 = red16(n2);
-        if (sl == 0 && p < k) cn[p] = n2;
+        cnr[cc] = red16(n2);
+        act[cc] = p < k;
     }
     for (int t = tid; t < KC; t += NT) pst[t] = kNever;
     __syncthreads();
     int c = 0;
     for (; c < k; ++c) {
+        const int par = c & 1;
+        // the wave's share of the pivot search, from the norms in registers:
+        // its groups' columns, then its four groups (lanes 0, 16, 32, 48)
         double rem = 0.0, best = -1.0;
         int bj = k;
-        if (tid < k && pst[tid] == kNever) {
-            rem = cn[tid];
-            best = cn[tid];
-            bj = tid;
+#pragma unroll
+        for (int cc = 0; cc < CPG; ++cc) {
+            const int p = grp + G * cc;
+            if (act[cc]) {
+                rem += cnr[cc];
+                if (cnr[cc] > best || (cnr[cc] == best && p < bj)) {
+                    best = cnr[cc];
+                    bj = p;
+                }
+            }
         }
-        pivot_reduce(rem, best, bj);
+        {
+            double rs[4], bs[4];
+            int js[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                rs[q] = readlane_d(rem, 16 * q);
+                bs[q] = readlane_d(best, 16 * q);
+                js[q] = __builtin_amdgcn_readlane(bj, 16 * q);
+            }
+            rem = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+            best = bs[0];
+            bj = js[0];
+#pragma unroll
+            for (int q = 1; q < 4; ++q)
+                if (bs[q] > best || (bs[q] == best && js[q] < bj)) {
+                    best = bs[q];
+                    bj = js[q];
+                }
+        }
         if (lane == 0) {
-            redv[wave] = rem;
-            redv[NW + wave] = best;
-            redi[wave] = bj;
+            redv[par][wave] = rem;
+            redv[par][NW + wave] = best;
+            redi[par][wave] = bj;
         }
         __syncthreads();
         rem = 0.0;
@@ -437,10 +432,10 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
         bj = k;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            rem += redv[w];
-            if (redv[NW + w] > best || (redv[NW + w] == best && redi[w] < bj)) {
-                best = redv[NW + w];
-                bj = redi[w];
+            rem += redv[par][w];
+            if (redv[par][NW + w] > best || (redv[par][NW + w] == best && redi[par][w] < bj)) {
+                best = redv[par][NW + w];
+                bj = redi[par][w];
             }
         }
         if (rem <= tol2) break;
@@ -467,6 +462,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
 #pragma unroll
             for (int cc = 0; cc < CPG; ++cc)
                 if (cc == oc) {
+                    act[cc] = false;
 #pragma unroll
                     for (int rr = 0; rr < RPS; ++rr) {
                         const int i = sl + 16 * rr;
@@ -491,13 +487,8 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
 #pragma unroll
         for (int rr = 0; rr < RPS; ++rr) vr[rr] = vsh[sl + 16 * rr];
         double w[CPG];
-        bool act[CPG];
 #pragma unroll
-        for (int cc = 0; cc < CPG; ++cc) {
-            const int p = grp + G * cc;
-            act[cc] = p < k && pst[p] == kNever;
-            w[cc] = 0.0;
-        }
+        for (int cc = 0; cc < CPG; ++cc) w[cc] = 0.0;
 #pragma unroll
         for (int rr = 0; rr < RPS; ++rr) {
             if (rr < rb0) continue;
@@ -520,14 +511,11 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
                 if (below) n2[cc] += a[cc][rr] * a[cc][rr];
             }
         }
+        // the new norms stay in registers; the next step's search needs no
+        // barrier before it (it writes the other parity's slots, and vsh and
+        // bet are rewritten only after its barrier)
 #pragma unroll
-        for (int cc = 0; cc < CPG; ++cc) w[cc] = n2[cc];
-#pragma unroll
-        for (int cc = 0; cc < CPG; ++cc) {
-            const double n2 = red16(w[cc]);
-            if (act[cc] && sl == 0) cn[grp + G * cc] = n2;
-        }
-        __syncthreads();
+        for (int cc = 0; cc < CPG; ++cc) cnr[cc] = red16(n2[cc]);
     }
     const int rr_rank = c;
     const int insufficient = (k - rr_rank < min_tail) && (k < (d.k_full < k_full ? d.k_full : k_full));
