@@ -189,7 +189,8 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
         const int count = tri(n);
         if (wave == 0) {
             trail_tiles(TS, b, 1, 0, 1);  // tile (b+1, b+1)
-            __threadfence_block();        // its update, written across lanes, is read back by rows
+            wave_sync();                  // its update, written across lanes, is read back by rows
+            __threadfence_block();        // (tiles in global memory above 176 columns)
             diag_tile(TS, b + 1, k, defl, inv, s_fail);
         } else {
             trail_tiles(TS, b, count, wave, kW - 1);
@@ -397,8 +398,8 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restr
 #pragma unroll
         for (int q = 0; q < 4; ++q) Ys[col * kYP + wr + lg + 4 * q] = acc[q];
         // diagonal block: lane li of the first row of 16 solves row wr + li
-        // left to right in registers (LDS operations of one wave complete in
-        // order, so it reads the values just written)
+        // left to right in registers, from the values the wave just wrote
+        wave_sync();
         if (lg == 0) {
             const double *Rd = Rb + (kT * b) * kTP;  // rows 16b.. of the staged block
             double y[kT];

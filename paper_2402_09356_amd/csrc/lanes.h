@@ -70,6 +70,16 @@ __device__ __forceinline__ double red16(double v) {
     return v;
 }
 
+// Orders LDS traffic between the lanes of one wave: writes before the call
+// are visible to reads after it in any lane of the same wave.  (The hardware
+// runs a wave's LDS operations in order; the fences stop the compiler from
+// moving accesses across the point.)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Broadcast of lane l's double to the whole wave (two v_readlane; l uniform).
 __device__ __forceinline__ double readlane_d(double v, int l) {
     const long long b = __double_as_longlong(v);

@@ -703,49 +703,89 @@ __global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict_
 // ------------------------------------------------- dense diagonal tiles --
 
 // Panels B_t[b0:b0+bs, :] <- L_bb^-1 B_t[b0:b0+bs, :], one work-group per
-// (panel, chunk of 64 columns); L_bb is the diagonal block of L (ld nb).
-__global__ __launch_bounds__(64) void k_trsm_block(const double *__restrict__ L, int ldl, int b0, int bs,
-                                                    const SmallDesc *__restrict__ descs) {
-    __shared__ double Ls[64 * 64];
+// (panel, chunk of 64 columns); L_bb is the diagonal block of L (ld nb).  The
+// block of L and the 64 x 64 block of B go through LDS; wave w owns columns
+// 16w..16w+15.  Four 16-row steps: the rows above are taken out with MFMA
+// (L rows x solved rows), then the 16 x 16 diagonal block is solved one
+// column per lane.  Rows past bs carry an identity diagonal (zero result).
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kTbP = 65;  // LDS pitch of both 64-row blocks
+
+__global__ __launch_bounds__(256) void k_trsm_block(const double *__restrict__ L, int ldl, int b0, int bs,
+                                                     const SmallDesc *__restrict__ descs) {
+    __shared__ double Ls[64 * kTbP];  // Ls[r + c * kTbP] = L[b0 + r][b0 + c]
+    __shared__ double Xs[64 * kTbP];  // Xs[r + c * kTbP]: row r, column c of the block of B
     const SmallDesc d = descs[blockIdx.y];
     const int cols = d.k_dev ? *d.k_dev : d.k;
-    const int c = blockIdx.x * 64 + threadIdx.x;
-    if (blockIdx.x * 64 >= cols) return;
+    const int c0 = blockIdx.x * 64;
+    if (c0 >= cols) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
     {
-        // the block of L, lane = row, sixteen columns a batch (loads in flight together)
-        const int r = threadIdx.x;
+        // L (lower, identity past bs) and B, lane = row: sixteen loads each in flight
+        double v[16];
 #pragma unroll
-        for (int q0 = 0; q0 < 64; q0 += 16) {
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int q = q0 + u;
-                v[u] = (r < bs && q < bs && r >= q) ? L[(b0 + r) + (int64_t)(b0 + q) * ldl] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) Ls[r + (q0 + u) * 64] = v[u];
+        for (int u = 0; u < 16; ++u) {
+            const int c = 4 * u + wave;  // columns wave, wave + 4, ...
+            v[u] = (lane < bs && c < bs) ? (lane >= c ? L[(b0 + lane) + (int64_t)(b0 + c) * ldl] : 0.0)
+                                         : ((lane == c) ? 1.0 : 0.0);
         }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) Ls[lane + (4 * u + wave) * kTbP] = v[u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = 4 * u + wave, col = c0 + c;
+            v[u] = (lane < bs && col < cols) ? d.Y[(int64_t)col * d.ldy + b0 + lane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) Xs[lane + (4 * u + wave) * kTbP] = v[u];
     }
     __syncthreads();
-    if (c >= cols) return;
-    double *y = d.Y + (int64_t)c * d.ldy + b0;
-    double x[64];
+    const int wc = 16 * wave;  // this wave's first column
 #pragma unroll
-    for (int r = 0; r < 64; ++r) x[r] = (r < bs) ? y[r] : 0.0;
-    // forward substitution, column-oriented: once x_r is final it is taken
-    // out of every later row (entries below bs are zero in Ls)
+    for (int s = 0; s < 4; ++s) {
+        const int r0 = 16 * s;
+        if (s > 0) {
+            // rows r0..r0+15 -= L[r0.., 0:r0] X[0:r0, cols]
+            v4d acc;
 #pragma unroll
-    for (int r = 0; r < 64; ++r) {
-        if (r < bs) {
-            const double xr = x[r] / Ls[r + r * 64];
-            x[r] = xr;
+            for (int q = 0; q < 4; ++q) acc[q] = Xs[(r0 + lg + 4 * q) + (wc + li) * kTbP];
+            v4d part = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < r0; kk += 4) {
+                const double av = Ls[(r0 + li) + (kk + lg) * kTbP];
+                const double bv = Xs[(kk + lg) + (wc + li) * kTbP];
+                part = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, part, 0, 0, 0);
+            }
+            acc -= part;
 #pragma unroll
-            for (int rp = r + 1; rp < 64; ++rp) x[rp] -= Ls[rp + r * 64] * xr;
+            for (int q = 0; q < 4; ++q) Xs[(r0 + lg + 4 * q) + (wc + li) * kTbP] = acc[q];
+        }
+        // diagonal block: lane li of the first row of 16 solves column wc + li
+        __syncthreads();  // the block's update, written across lanes, is read back by columns
+        if (lg == 0) {
+            double y[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) y[i] = Xs[(r0 + i) + (wc + li) * kTbP];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const double xi = y[i] / Ls[(r0 + i) + (r0 + i) * kTbP];
+                y[i] = xi;
+#pragma unroll
+                for (int j = i + 1; j < 16; ++j) y[j] -= Ls[(r0 + j) + (r0 + i) * kTbP] * xi;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) Xs[(r0 + i) + (wc + li) * kTbP] = y[i];
+        }
+        __syncthreads();  // the solved rows are read across lanes by the next step
+    }
+    {
+        // write back, lane = row
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = 4 * u + wave, col = c0 + c;
+            if (lane < bs && col < cols) d.Y[(int64_t)col * d.ldy + b0 + lane] = Xs[lane + c * kTbP];
         }
     }
-#pragma unroll
-    for (int r = 0; r < 64; ++r)
-        if (r < bs) y[r] = x[r];
 }
 
 }  // namespace
@@ -874,7 +914,7 @@ tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, co
             const double d = bs;
             // bs^2 flops per right-hand side; the block of L once, each column read and written once
             KTimer kt(cls, s, d * d * cols_sum, 8.0 * (d * (d + 1.0) / 2.0 + 2.0 * d * cols_sum), exact);
-            hipLaunchKernelGGL(k_trsm_block, dim3((unsigned)cdiv(max_cols, 64), count), dim3(64), 0, s, L, nb,
+            hipLaunchKernelGGL(k_trsm_block, dim3((unsigned)cdiv(max_cols, 64), count), dim3(256), 0, s, L, nb,
                                b0, bs, d_descs);
         }
         if (rest > 0)
