@@ -278,6 +278,15 @@ struct Ctx {
         arena_used += bytes;
         return d;
     }
+    // Wait for the main stream only (the side stream keeps running); staged
+    // descriptors stay where they are, since the side stream may still read
+    // some of them.
+    tlr_status sync_main() {
+        TLR_HIP(hipStreamSynchronize(s));
+        in_flight = false;
+        ktimer_poll();
+        return TLR_OK;
+    }
     tlr_status sync_reset() {
         TLR_HIP(hipStreamSynchronize(s));
         TLR_TRY(drain_side());
@@ -1010,14 +1019,26 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
         }
         // dense Cholesky of the updated diagonal tile, beside the
         // recompression of the tiles below (which never reads it); only the
-        // triangular solves at the end of the column need its factor
+        // triangular solves at the end of the column need its factor.  The
+        // side stream is forked here, after the diagonal update; its launches
+        // are issued once the main stream has the column's first batch of
+        // work queued, so that their host-side cost does not starve it.
+        hipStream_t side_s = nullptr;
+        const GemmDesc *dpd = nullptr;
         {
             std::vector<GemmDesc> pd((size_t)cdiv(nb, 64));
             potrf_tile_descs(c.diag(j), nb, pd.data());
-            TLR_PUSH(dpd, c, pd);
+            dpd = c.push(pd);
+            if (!dpd) return TLR_E_NOMEM;
             TLR_TRY(c.flush());
-            TLR_TRY(potrf_tile(c.diag(j), nb, j, c.params(), dpd, c.fork()));
+            side_s = c.fork();
         }
+        bool diag_issued = false;
+        auto issue_diag = [&]() -> tlr_status {
+            if (diag_issued) return TLR_OK;
+            diag_issued = true;
+            return potrf_tile(c.diag(j), nb, j, c.params(), dpd, side_s);
+        };
         // Schur complement of the tiles below, re-compressed once
         std::vector<int> rows;
         for (int i = j + 1; i < nt; ++i) rows.push_back(i);
@@ -1125,9 +1146,16 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                     }
                     if (!jobs.empty())
                         TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, false, q1_passes(p, hb.dp.sigma2, tol)));
+                    TLR_TRY(issue_diag());
                     Ctx::StatRead sr;
                     TLR_TRY(c.read_stats(jobs, sr));
-                    TLR_TRY(c.sync_reset());
+                    // the side stream's diagonal Cholesky may still run: wait
+                    // for the main stream alone unless the descriptor area
+                    // must be recycled
+                    if (c.desc_used > p->desc_bytes / 2)
+                        TLR_TRY(c.sync_reset());
+                    else
+                        TLR_TRY(c.sync_main());
                     if (!jobs.empty() && sr.status != 0) failed = true;
                     std::vector<int32_t> st(4 * jobs.size());
                     for (size_t q = 0; q < jobs.size(); ++q)
@@ -1180,6 +1208,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             }
             c.arena_used = mark;
         }
+        TLR_TRY(issue_diag());
         if (failed) break;
         // the triangular solves need the diagonal factor from the side stream
         TLR_TRY(c.join());
@@ -1205,10 +1234,10 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             if (!dg) return TLR_E_NOMEM;
             TLR_LAUNCH(c, trsm_left_lower(c.diag(j), nb, dsd, sd.data(), (int)sd.size(), maxc, dg, nullptr, s));
         }
-        // no wait here: the next column's first launches queue behind these
-        // (its status read-back drains both streams); the descriptor area is
-        // recycled early only when it runs half full
-        if (c.desc_used > p->desc_bytes / 2) TLR_TRY(c.sync_reset());
+        // no wait here: the next column's first launches queue behind these.
+        // The descriptor area is recycled here, where the side stream has
+        // finished (the main stream waited for it), once a quarter is used.
+        if (c.desc_used > p->desc_bytes / 4) TLR_TRY(c.sync_reset());
     }
     TLR_TRY(c.sync_reset());
     TLR_TRY(c.store_dense());
