@@ -154,10 +154,10 @@ __device__ __forceinline__ void trail_tiles(double *TS, int b, int count, int t0
 // (b+1, b+1) first and factors it at once, while the other waves update the
 // rest, so each diagonal factorisation (a chain of sixteen dependent pivots)
 // overlaps the previous step's updates.
-template <bool LDS>
+template <bool LDS, int NTH>
 __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, int *s_fail) {
     const int tid = threadIdx.x, wave = tid >> 6;
-    constexpr int kW = kThreads / 64;
+    constexpr int kW = NTH / 64;
     if (wave == 0) diag_tile(TS, 0, k, defl, inv, s_fail);
     __syncthreads();
     if (*s_fail) return *s_fail;
@@ -167,7 +167,7 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
         // panel rows: x L_bb^T = a
         const double *D = TS + (tri(b) + b) * kTW;
 #pragma unroll 1
-        for (int rr = tid; rr < kT * n; rr += kThreads) {
+        for (int rr = tid; rr < kT * n; rr += NTH) {
             const int ti = b + 1 + (rr >> 4), r = rr & 15;
             double *P = TS + (tri(ti) + b) * kTW;
             double a[kT];
@@ -201,37 +201,49 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
     return 0;
 }
 
-template <bool LDS>
+// Tile t of the lower triangle (row by row): (i, j) with t = i(i+1)/2 + j.
+__device__ __forceinline__ void tile_rc(int t, int &i, int &j) {
+    int ip = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (tri(ip + 1) <= t) ++ip;
+    while (tri(ip) > t) --ip;
+    i = ip;
+    j = t - tri(ip);
+}
+
+// NTH threads: NTH / 256 tiles a pass, a batch of passes' loads in flight
+// together.
+template <bool LDS, int NTH>
 __device__ __forceinline__ void load_tiles(double *TS, int T, int k, const double *A, int64_t lda, double shift) {
+    constexpr int TPP = NTH / 256, BATCH = 32 / TPP;
     const int tid = threadIdx.x;
-    const int r = tid & 15, c = tid >> 4;  // 256 threads: one tile per pass
+    const int r = tid & 15, c = (tid >> 4) & 15, sub = tid >> 8;
     const int nt = tri(T);
-    int ti = 0, tj = 0;  // tile of the batch's first index
-    // thirty-two tiles a batch: their loads are in flight together
 #pragma unroll 1
-    for (int t0 = 0; t0 < nt; t0 += 32) {
-        double v[32];
+    for (int t0 = 0; t0 < nt; t0 += BATCH * TPP) {
+        double v[BATCH];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
+        for (int u = 0; u < BATCH; ++u) {
+            const int t = t0 + TPP * u + sub;
+            int ti, tj;
+            tile_rc(t, ti, tj);
             const int gr = kT * ti + r, gc = kT * tj + c;
             if (gr < k && gc < k)
                 v[u] = (gr >= gc) ? A[gr + (int64_t)gc * lda] + ((gr == gc) ? shift : 0.0) : 0.0;
             else
                 v[u] = (gr == gc) ? 1.0 : 0.0;
-            if (++tj > ti) {
-                ++ti;
-                tj = 0;
-            }
         }
 #pragma unroll
-        for (int u = 0; u < 32; ++u)
-            if (t0 + u < nt) TS[(t0 + u) * kTW + r + kTP * c] = v[u];
+        for (int u = 0; u < BATCH; ++u) {
+            const int t = t0 + TPP * u + sub;
+            if (t < nt) TS[t * kTW + r + kTP * c] = v[u];
+        }
     }
 }
 
+template <int NTH>
 __device__ __forceinline__ void store_r(const double *TS, int k, double *R, int64_t ldr) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int q = wave; q < k; q += kThreads / 64)
+    for (int q = wave; q < k; q += NTH / 64)
         for (int r = lane; r < k; r += 64) {
             double v = 0.0;
             if (r <= q) v = TS[(tri(q >> 4) + (r >> 4)) * kTW + (q & 15) + kTP * (r & 15)];
@@ -239,8 +251,11 @@ __device__ __forceinline__ void store_r(const double *TS, int k, double *R, int6
         }
 }
 
-__global__ __launch_bounds__(kThreads) void k_chol_small(const SmallDesc *__restrict__ descs, int mode,
-                                                          DevParams *params, int lds_tiles) {
+constexpr int kCholThreads = 512;  // eight waves: seven update while one factors
+
+__global__ __launch_bounds__(kCholThreads) void k_chol_small(const SmallDesc *__restrict__ descs, int mode,
+                                                              DevParams *params, int lds_tiles) {
+    constexpr int NTH = kCholThreads, kW = NTH / 64;
     extern __shared__ double smem[];
     const SmallDesc d = descs[blockIdx.x];
     const int k = d.k_dev ? *d.k_dev : d.k;
@@ -256,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_small(const SmallDesc *__rest
     double shift = 0.0, defl = 0.0;
     if (mode != 0) {
         double v = (mode == 1) ? 0.0 : 0.0;
-        for (int c = tid; c < k; c += kThreads) {
+        for (int c = tid; c < k; c += NTH) {
             const double g = d.A[c + (int64_t)c * d.lda];
             v = (mode == 1) ? v + g : fmax(v, g);
         }
@@ -266,29 +281,33 @@ __global__ __launch_bounds__(kThreads) void k_chol_small(const SmallDesc *__rest
     if (tid == 0) *s_fail = 0;
     __syncthreads();
     if (mode == 1) {
-        const double tr = red[0] + red[1] + red[2] + red[3];
+        double tr = 0.0;
+#pragma unroll
+        for (int w = 0; w < kW; ++w) tr += red[w];
         shift = 11.0 * ((double)d.m * k + (double)k * (k + 1)) * 1.1102230246251565e-16 * tr;
         defl = 1e-300;
     } else if (mode == 2) {
-        const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        double mx = red[0];
+#pragma unroll
+        for (int w = 1; w < kW; ++w) mx = fmax(mx, red[w]);
         defl = (mx > 0.0) ? 1e-12 * mx : 1e-300;
     }
     int fail;
     if (T <= lds_tiles) {
-        load_tiles<true>(smem, T, k, d.A, d.lda, shift);
+        load_tiles<true, NTH>(smem, T, k, d.A, d.lda, shift);
         __syncthreads();
-        fail = chol_tiles<true>(smem, T, k, defl, inv, s_fail);
-        if (!fail) store_r(smem, k, d.R, d.ldr);
+        fail = chol_tiles<true, NTH>(smem, T, k, defl, inv, s_fail);
+        if (!fail) store_r<NTH>(smem, k, d.R, d.ldr);
     } else {
-        load_tiles<false>(d.X, T, k, d.A, d.lda, shift);
+        load_tiles<false, NTH>(d.X, T, k, d.A, d.lda, shift);
         __syncthreads();
-        fail = chol_tiles<false>(d.X, T, k, defl, inv, s_fail);
-        if (!fail) store_r(d.X, k, d.R, d.ldr);
+        fail = chol_tiles<false, NTH>(d.X, T, k, defl, inv, s_fail);
+        if (!fail) store_r<NTH>(d.X, k, d.R, d.ldr);
     }
     if (fail) {
         if (tid == 0) set_status(params, TLR_NOT_SPD, -100 - d.tile_i, -100 - d.tile_j);
         // an identity factor keeps downstream arithmetic finite
-        for (int e = tid; e < k * k; e += kThreads) {
+        for (int e = tid; e < k * k; e += NTH) {
             const int r = e % k, q = e / k;
             d.R[r + (int64_t)q * d.ldr] = (r == q) ? 1.0 : 0.0;
         }
@@ -511,9 +530,9 @@ __global__ __launch_bounds__(kThreads) void k_potrf_block(double *A, int ld, int
     if (tid == 0) s_fail = 0;
     const int T = (bs + kT - 1) / kT;
     double *Ab = A + b0 + (int64_t)b0 * ld;
-    load_tiles<true>(ts, T, bs, Ab, ld, 0.0);
+    load_tiles<true, kThreads>(ts, T, bs, Ab, ld, 0.0);
     __syncthreads();
-    const int fail = chol_tiles<true>(ts, T, bs, 0.0, inv, &s_fail);
+    const int fail = chol_tiles<true, kThreads>(ts, T, bs, 0.0, inv, &s_fail);
     if (fail) {
         if (tid == 0) set_status(params, TLR_NOT_SPD, tile, tile);
         return;
@@ -617,7 +636,7 @@ tlr_status chol_small(const SmallDesc *d_descs, int count, int max_k, int mode, 
     const int lds_tiles = tmax < kCholLdsTiles ? tmax : kCholLdsTiles;
     const size_t lds = sizeof(double) * ((size_t)tri(lds_tiles) * kTW + kT + 8) + 16;
     KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
-    hipLaunchKernelGGL(k_chol_small, dim3(count), dim3(kThreads), lds, s, d_descs, mode, params, lds_tiles);
+    hipLaunchKernelGGL(k_chol_small, dim3(count), dim3(kCholThreads), lds, s, d_descs, mode, params, lds_tiles);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }
