@@ -607,7 +607,8 @@ tlr_status potrf_tile(double *A, int nb, int tile, DevParams *params, const Gemm
                 hipLaunchKernelGGL(k_potrf_panel, dim3((unsigned)cdiv(rest, kThreads)), dim3(kThreads), 0, s, A, nb,
                                    b0, bs, nb, params);
             }
-            TLR_TRY(gemm_batched(false, true, d_desc + b, 1, rest, rest, s));
+            // the trailing update: only its lower triangle is ever read
+            TLR_TRY(gemm_batched(false, true, d_desc + b, 1, rest, rest, s, nullptr, true));
         }
     }
     TLR_HIP(hipGetLastError());

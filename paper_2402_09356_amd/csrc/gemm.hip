@@ -47,15 +47,17 @@ __device__ inline void load_slice(Slice &sl, const double *__restrict__ A, int64
     }
 }
 
+// lower_only: blocks wholly above the diagonal are skipped (products whose
+// consumer reads only the lower triangle: Gram matrices, symmetric updates).
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *descs, int tiles_n) {
+__global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *descs, int tiles_n, int lower_only) {
     const GemmDesc d = descs[blockIdx.y];
     const int M = d.M_dev ? *d.M_dev : d.M;
     const int N = d.N_dev ? *d.N_dev : d.N;
     const int K = d.K_dev ? *d.K_dev : d.K;
     const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     const int m0 = tm * BM, n0 = tn * BN;
-    if (m0 >= M || n0 >= N) return;
+    if (m0 >= M || n0 >= N || (lower_only && n0 > m0)) return;
 
     __shared__ double red[4][BM * BN];
 
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(const GemmDesc *descs, int til
 }  // namespace
 
 tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int count, int max_m,
-                        int max_n, hipStream_t s, const GemmDesc *h_descs) {
+                        int max_n, hipStream_t s, const GemmDesc *h_descs, bool lower_only) {
     if (count <= 0 || max_m <= 0 || max_n <= 0) return TLR_OK;
     const int tiles_m = (int)cdiv(max_m, BM), tiles_n = (int)cdiv(max_n, BN);
     if (count > 65535) return TLR_E_UNSUPPORTED;
@@ -232,8 +234,11 @@ tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int
             const GemmDesc &g = h_descs[t];
             if (g.M_dev || g.N_dev || g.K_dev) exact = false;
             const double M = g.M, N = g.N, K = g.K;
-            flops += 2.0 * M * N * K;
-            bytes += 8.0 * (M * K + K * N + M * N * (g.beta != 0.0 ? 2.0 : 1.0));
+            // a lower-only product computes the M(M+1)/2 entries on and below
+            // the diagonal (M = N for every such product here)
+            const double outs = lower_only ? M * (M + 1.0) / 2.0 : M * N;
+            flops += 2.0 * outs * K;
+            bytes += 8.0 * (M * K + K * N + outs * (g.beta != 0.0 ? 2.0 : 1.0));
         }
     // tall products (many rows of C) go to the LDS-staged kernel, which reads
     // both operands along their contiguous index and needs no final
@@ -241,7 +246,7 @@ tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int
     // 64 x 32; short ones keep the K-split kernel, which spreads a long K over
     // four waves (Gram matrices, small sketches)
     const int row_blocks = (int)cdiv(max_m, 64);
-    if (!trans_b && max_m >= kTallM && (int64_t)row_blocks * count >= kTallBlocks) {
+    if (!lower_only && !trans_b && max_m >= kTallM && (int64_t)row_blocks * count >= kTallBlocks) {
         static const int cls_t = ktimer_class("k_gemm_lds<T,N>"), cls_w = ktimer_class("k_gemm_lds<N,N>");
         KTimer kt(trans_a ? cls_t : cls_w, s, flops, bytes, exact);
         if (max_n > 32 && (trans_a || max_n <= 64)) {
@@ -265,13 +270,13 @@ tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int
     KTimer kt(cls[(trans_a ? 2 : 0) + (trans_b ? 1 : 0)], s, flops, bytes, exact);
     const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)count), block(256);
     if (!trans_a && !trans_b)
-        hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, block, 0, s, d_descs, tiles_n);
+        hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, block, 0, s, d_descs, tiles_n, lower_only ? 1 : 0);
     else if (!trans_a && trans_b)
-        hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, block, 0, s, d_descs, tiles_n);
+        hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, block, 0, s, d_descs, tiles_n, lower_only ? 1 : 0);
     else if (trans_a && !trans_b)
-        hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, block, 0, s, d_descs, tiles_n);
+        hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, block, 0, s, d_descs, tiles_n, lower_only ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, block, 0, s, d_descs, tiles_n);
+        hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, block, 0, s, d_descs, tiles_n, lower_only ? 1 : 0);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }

@@ -27,7 +27,8 @@ struct GemmDesc {
 // h_descs: optional host copy of the descriptors, used only to count the
 // launch's work for the launch timer.
 tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int count, int max_m,
-                        int max_n, hipStream_t s, const GemmDesc *h_descs = nullptr);
+                        int max_n, hipStream_t s, const GemmDesc *h_descs = nullptr,
+                        bool lower_only = false);
 
 // Small dense problems, one work-group each.
 struct SmallDesc {

@@ -383,9 +383,11 @@ struct StagedGemm {
     const GemmDesc *h = nullptr;
     int count = 0, mm = 0, mn = 0;
     bool ta = false, tb = false;
+    bool lower = false;  // only the lower triangle of each product is needed
 };
 
-tlr_status stage_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v, StagedGemm *out) {
+tlr_status stage_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v, StagedGemm *out,
+                       bool lower = false) {
     *out = StagedGemm{};
     if (v.empty()) return TLR_OK;
     if (v.size() > 65535) return TLR_E_UNSUPPORTED;
@@ -396,13 +398,13 @@ tlr_status stage_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v,
     }
     auto *d = c.push(v.data(), v.size());
     if (!d) return TLR_E_NOMEM;
-    *out = StagedGemm{d, v.data(), (int)v.size(), mm, mn, ta, tb};
+    *out = StagedGemm{d, v.data(), (int)v.size(), mm, mn, ta, tb, lower};
     return TLR_OK;
 }
 
 tlr_status launch_staged(Ctx &c, const StagedGemm &g) {
     if (g.count == 0 || g.mm <= 0 || g.mn <= 0) return TLR_OK;
-    TLR_LAUNCH(c, gemm_batched(g.ta, g.tb, g.d, g.count, g.mm, g.mn, c.s, g.h));
+    TLR_LAUNCH(c, gemm_batched(g.ta, g.tb, g.d, g.count, g.mm, g.mn, c.s, g.h, g.lower));
     return TLR_OK;
 }
 
@@ -536,7 +538,8 @@ tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int pa
         }
     }
     StagedGemm sg;
-    TLR_TRY(stage_gemms(c, true, false, gram, &sg));
+    // the Cholesky factorisation reads only the Gram matrix's lower triangle
+    TLR_TRY(stage_gemms(c, true, false, gram, &sg, true));
     TLR_PUSH(dsd, c, sd);
     StagedGemm sa, sb, sc;
     std::vector<GemmDesc> a, b, d2;
@@ -586,6 +589,10 @@ int q1_passes(const tlr_plan_s *p, double sigma2, double tol) {
 tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, int Rj, bool exact_svd,
                 int passes_q1) {
     if (jobs.empty()) return TLR_OK;
+    // widest sample first: its work-groups, the longest, are dispatched
+    // first in every batched launch below (the order of the results is not
+    // affected)
+    std::stable_sort(jobs.begin(), jobs.end(), [](const Job &a, const Job &b) { return a.k > b.k; });
     const int nb = c.p->nb;
     int kmx = 0;
     for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
