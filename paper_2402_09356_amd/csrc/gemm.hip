@@ -49,8 +49,10 @@ __device__ inline void load_slice(Slice &sl, const double *__restrict__ A, int64
 
 // lower_only: blocks wholly above the diagonal are skipped (products whose
 // consumer reads only the lower triangle: Gram matrices, symmetric updates).
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *descs, int tiles_n, int lower_only) {
+// NW waves split K (four, or eight for the Gram matrices, whose K is the
+// long tile edge and whose blocks are few).
+template <bool TA, bool TB, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gemm_f64(const GemmDesc *descs, int tiles_n, int lower_only) {
     const GemmDesc d = descs[blockIdx.y];
     const int M = d.M_dev ? *d.M_dev : d.M;
     const int N = d.N_dev ? *d.N_dev : d.N;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *descs, int til
     const int m0 = tm * BM, n0 = tn * BN;
     if (m0 >= M || n0 >= N || (lower_only && n0 > m0)) return;
 
-    __shared__ double red[4][BM * BN];
+    __shared__ double red[NW][BM * BN];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -77,8 +79,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *descs, int til
     const int nsl = (K + BK - 1) / BK;
     Slice cur, nxt;
     if (wave < nsl) load_slice<TA, TB>(cur, A, lda, B, ldb, m0, n0, wave * BK, M, N, K, li, lk);
-    for (int s = wave; s < nsl; s += 4) {
-        if (s + 4 < nsl) load_slice<TA, TB>(nxt, A, lda, B, ldb, m0, n0, (s + 4) * BK, M, N, K, li, lk);
+    for (int s = wave; s < nsl; s += NW) {
+        if (s + NW < nsl) load_slice<TA, TB>(nxt, A, lda, B, ldb, m0, n0, (s + NW) * BK, M, N, K, li, lk);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -102,11 +104,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmDesc *descs, int til
     const int64_t ldc = d.ldc;
     const double alpha = d.alpha, beta = d.beta;
 #pragma unroll
-    for (int e = tid; e < BM * BN; e += 256) {
+    for (int e = tid; e < BM * BN; e += NW * 64) {
         const int r = e % BM, c = e / BM;
         const int gm = m0 + r, gn = n0 + c;
         if (gm < M && gn < N) {
-            const double v = alpha * (((red[0][e] + red[1][e]) + red[2][e]) + red[3][e]);
+            double sum = red[0][e];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) sum += red[w][e];
+            const double v = alpha * sum;
             double *cp = C + gm + gn * ldc;
             *cp = (beta == 0.0) ? v : v + beta * (*cp);
         }
@@ -268,15 +273,29 @@ tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int
         return TLR_OK;
     }
     KTimer kt(cls[(trans_a ? 2 : 0) + (trans_b ? 1 : 0)], s, flops, bytes, exact);
-    const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)count), block(256);
-    if (!trans_a && !trans_b)
-        hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, block, 0, s, d_descs, tiles_n, lower_only ? 1 : 0);
-    else if (!trans_a && trans_b)
-        hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, block, 0, s, d_descs, tiles_n, lower_only ? 1 : 0);
-    else if (trans_a && !trans_b)
-        hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, block, 0, s, d_descs, tiles_n, lower_only ? 1 : 0);
-    else
-        hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, block, 0, s, d_descs, tiles_n, lower_only ? 1 : 0);
+    const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)count);
+    const int lo = lower_only ? 1 : 0;
+    if (lower_only) {
+        const dim3 block(512);
+        if (!trans_a && !trans_b)
+            hipLaunchKernelGGL((k_gemm_f64<false, false, 8>), grid, block, 0, s, d_descs, tiles_n, lo);
+        else if (!trans_a && trans_b)
+            hipLaunchKernelGGL((k_gemm_f64<false, true, 8>), grid, block, 0, s, d_descs, tiles_n, lo);
+        else if (trans_a && !trans_b)
+            hipLaunchKernelGGL((k_gemm_f64<true, false, 8>), grid, block, 0, s, d_descs, tiles_n, lo);
+        else
+            hipLaunchKernelGGL((k_gemm_f64<true, true, 8>), grid, block, 0, s, d_descs, tiles_n, lo);
+    } else {
+        const dim3 block(256);
+        if (!trans_a && !trans_b)
+            hipLaunchKernelGGL((k_gemm_f64<false, false, 4>), grid, block, 0, s, d_descs, tiles_n, lo);
+        else if (!trans_a && trans_b)
+            hipLaunchKernelGGL((k_gemm_f64<false, true, 4>), grid, block, 0, s, d_descs, tiles_n, lo);
+        else if (trans_a && !trans_b)
+            hipLaunchKernelGGL((k_gemm_f64<true, false, 4>), grid, block, 0, s, d_descs, tiles_n, lo);
+        else
+            hipLaunchKernelGGL((k_gemm_f64<true, true, 4>), grid, block, 0, s, d_descs, tiles_n, lo);
+    }
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }
