@@ -3,7 +3,8 @@
 //    Fukaya, Kannan, Nakatsukasa, Zhang, Yamamoto, SIAM J. Sci. Comput. 2020;
 //    deflation of null directions), right-looking over 16 x 16 tiles;
 //  * k_trsm_rows: Y <- Y R^-1 for the m x k panel, 16 columns at a time
-//    (the row block held in LDS; k_trsm_rows_wide for k above 192).
+//    (the row block held in LDS; k_trsm_rows_wide for k above 192 and for
+//    batches too large for one LDS-bound work-group per compute unit).
 //
 // Tiles.  The lower triangle is held as 16 x 16 tiles, tile (i, j), i >= j,
 // at index i(i+1)/2 + j, each stored column-major with a column pitch of 17
