@@ -59,7 +59,11 @@ __device__ inline double wave_max(double v) {
 }
 
 // One wave factors diagonal tile b in registers (lane r holds row r); sets
-// *s_fail on failure.  Called by wave 0 only.
+// *s_fail on failure.  Called by wave 0 only.  Step c broadcasts column c as
+// it stands (a_qc, before scaling) and updates the rows below with
+// a_rq -= (a_rc / a_cc) a_qc, so the broadcasts overlap the pivot's square
+// root instead of following it; the loop has no branch, so the scheduler can
+// overlap one step's updates with the next step's pivot.
 __device__ __forceinline__ void diag_tile(double *TS, int b, int k, double defl, double *inv, int *s_fail) {
     const int lane = threadIdx.x & 63;
     double *D = TS + (tri(b) + b) * kTW;
@@ -69,30 +73,35 @@ __device__ __forceinline__ void diag_tile(double *TS, int b, int k, double defl,
     for (int q = 0; q < kT; ++q) a[q] = D[r + kTP * q];
     const double dstart = D[r + kTP * r];  // this row's diagonal entry before the tile's steps
     int fail = 0;
+    double my_inv = 0.0;  // 1 / L_rr, kept by lane r
 #pragma unroll
     for (int c = 0; c < kT; ++c) {
+        // entry (q, c) of the column sits in lane q of every row
+        double aq[kT];
+#pragma unroll
+        for (int q = c + 1; q < kT; ++q) aq[q] = row_bcast_at(a[c], q);
         const double piv = readlane_d(a[c], c);
+        const double d0 = readlane_d(dstart, c);
         const int gc = kT * b + c;
-        // the cases resolve by selects, off the pivot's critical path:
-        // padding (1), failure or dead direction (0), else sqrt(piv)
+        // the cases resolve by selects: padding (1), failure or dead
+        // direction (0), else sqrt(piv)
         const double ivr = rsqrt(piv);
         const bool pad = gc >= k;
-        const bool bad = !isfinite(piv) || (defl == 0.0 && !(piv > kPivotLoss * readlane_d(dstart, c)));
-        const bool zero = bad || (defl > 0.0 && piv <= defl);
-        if (bad && !pad && !fail) fail = gc + 1;
+        // (bitwise: no short-circuit branch in the pivot chain)
+        const bool bad = !isfinite(piv) | ((defl == 0.0) & !(piv > kPivotLoss * d0));
+        const bool zero = bad | ((defl > 0.0) & (piv <= defl));
+        fail = (bad & !pad & (fail == 0)) ? gc + 1 : fail;
         const double iv = pad ? 1.0 : (zero ? 0.0 : ivr);
         const double lcc = pad ? 1.0 : (zero ? 0.0 : piv * ivr);
-        const double lrc = (r == c) ? lcc : ((r > c) ? a[c] * iv : 0.0);
-        a[c] = lrc;
-        // entry (q, c) of the new column sits in lane q of every row
-        double lq[kT];
+        const double lrc = a[c] * iv;
+        const double t = lrc * iv;  // a_rc / a_cc (0 for a dead direction)
+        a[c] = (r == c) ? lcc : ((r > c) ? lrc : 0.0);
 #pragma unroll
-        for (int q = c + 1; q < kT; ++q) lq[q] = row_bcast_at(lrc, q);
-#pragma unroll
-        for (int q = c + 1; q < kT; ++q) a[q] -= lrc * lq[q];
-        if (lane == c) inv[c] = iv;
+        for (int q = c + 1; q < kT; ++q) a[q] -= t * aq[q];
+        my_inv = (r == c) ? iv : my_inv;
     }
     if (lane < kT) {
+        inv[r] = my_inv;
 #pragma unroll
         for (int q = 0; q < kT; ++q) D[r + kTP * q] = (q <= r) ? a[q] : 0.0;
     }

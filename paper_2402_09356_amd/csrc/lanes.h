@@ -16,9 +16,11 @@ constexpr int kDppHalfMirror = 0x141;  // lane l reads 7 - l within its 8 lanes
 constexpr int kDppMirror = 0x140;      // lane l reads 15 - l within its row
 constexpr int kDppRowBcast0 = 0x150;   // + j: every lane of a row reads the row's lane j
 
+// Every lane is written from a valid source, so the destination's old value
+// is never kept: the plain move form needs no initialisation of it.
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
 }
 
 template <int CTRL>
