@@ -43,10 +43,20 @@ constexpr int kCholLdsTiles = 11;
 // zero, i.e. the matrix is singular to working precision.
 constexpr double kPivotLoss = 1e-14;
 constexpr int kThreads = 256;
+constexpr int kPanelU = 6;  // groups of four panel rows a wave solves together
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __host__ inline int tri(int i) { return i * (i + 1) / 2; }
+
+// The largest i with tri(i) <= t (0 <= t < 2^20): the single-precision root
+// is within one of it, and one select each way corrects it.
+__device__ __forceinline__ int tri_root(int t) {
+    int i = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    i += (tri(i + 1) <= t) ? 1 : 0;
+    i -= (tri(i) > t) ? 1 : 0;
+    return i;
+}
 
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -115,9 +125,7 @@ __device__ __forceinline__ void trail_tiles(double *TS, int b, int count, int t0
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lg = lane >> 4;
     auto tile_of = [&](int t, int &i, int &j) {
-        int ip = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while (tri(ip + 1) <= t) ++ip;
-        while (tri(ip) > t) --ip;
+        const int ip = tri_root(t);
         i = b + 1 + ip;
         j = b + 1 + (t - tri(ip));
     };
@@ -174,26 +182,46 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
 #pragma unroll 1
     for (int b = 0; b + 1 < T; ++b) {
         const int n = T - b - 1;
-        // panel rows: x L_bb^T = a
-        const double *D = TS + (tri(b) + b) * kTW;
+        // panel rows: x L_bb^T = a.  Lane j of each row of 16 holds column j
+        // of one panel row, so column c of the solution crosses the row by
+        // DPP and row j of L_bb stays in registers: four panel rows a wave
+        // instruction, kPanelU groups of four in flight per wave.  Lane j
+        // keeps its entry unscaled and scales it once its column is done,
+        // which gives the same value as scaling at step j: the strictly lower
+        // row of L_bb leaves it unchanged afterwards.  Each entry takes the
+        // same operations in the same order as a row-by-row forward
+        // substitution.
+        {
+            const int li = tid & 15, lg = (tid >> 4) & 3;
+            const double *D = TS + (tri(b) + b) * kTW;
+            double lj[kT];  // row li of L_bb, strictly lower part
+#pragma unroll
+            for (int c = 0; c < kT; ++c) lj[c] = (c < li) ? D[li + kTP * c] : 0.0;
+            const double ivj = inv[li];
+            const int groups = 4 * n;
 #pragma unroll 1
-        for (int rr = tid; rr < kT * n; rr += NTH) {
-            const int ti = b + 1 + (rr >> 4), r = rr & 15;
-            double *P = TS + (tri(ti) + b) * kTW;
-            double a[kT];
+            for (int g0 = wave; g0 < groups; g0 += kW * kPanelU) {
+                double x[kPanelU];
+                double *px[kPanelU];
 #pragma unroll
-            for (int q = 0; q < kT; ++q) a[q] = P[r + kTP * q];
-            // column-oriented: each entry takes the same subtractions in the
-            // same order as a row dot product, with a short dependent chain
+                for (int v = 0; v < kPanelU; ++v) {
+                    const int g = g0 + kW * v;
+                    const int row = 4 * (g < groups ? g : 0) + lg;  // row of the panel
+                    px[v] = TS + (tri(b + 1 + (row >> 4)) + b) * kTW + (row & 15) + kTP * li;
+                    x[v] = (g < groups) ? *px[v] : 0.0;
+                }
 #pragma unroll
-            for (int c = 0; c < kT; ++c) {
-                const double xc = a[c] * inv[c];
-                a[c] = xc;
+                for (int c = 0; c < kT; ++c) {
 #pragma unroll
-                for (int q = c + 1; q < kT; ++q) a[q] -= xc * D[q + kTP * c];
+                    for (int v = 0; v < kPanelU; ++v) {
+                        const double xc = row_bcast_at(x[v] * ivj, c);
+                        x[v] -= xc * lj[c];
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < kPanelU; ++v)
+                    if (g0 + kW * v < groups) *px[v] = x[v] * ivj;
             }
-#pragma unroll
-            for (int q = 0; q < kT; ++q) P[r + kTP * q] = a[q];
         }
         __syncthreads();
         const int count = tri(n);
@@ -213,15 +241,14 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
 
 // Tile t of the lower triangle (row by row): (i, j) with t = i(i+1)/2 + j.
 __device__ __forceinline__ void tile_rc(int t, int &i, int &j) {
-    int ip = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while (tri(ip + 1) <= t) ++ip;
-    while (tri(ip) > t) --ip;
-    i = ip;
-    j = t - tri(ip);
+    i = tri_root(t);
+    j = t - tri(i);
 }
 
 // NTH threads: NTH / 256 tiles a pass, a batch of passes' loads in flight
-// together.
+// together.  The loads are unconditional (entries outside the lower triangle
+// of the k x k matrix read A[0]) and the selects come after the batch, so no
+// branch separates a load from the next one.
 template <bool LDS, int NTH>
 __device__ __forceinline__ void load_tiles(double *TS, int T, int k, const double *A, int64_t lda, double shift) {
     constexpr int TPP = NTH / 256, BATCH = 32 / TPP;
@@ -231,21 +258,27 @@ __device__ __forceinline__ void load_tiles(double *TS, int T, int k, const doubl
 #pragma unroll 1
     for (int t0 = 0; t0 < nt; t0 += BATCH * TPP) {
         double v[BATCH];
+        int gr[BATCH], gc[BATCH];
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
             const int t = t0 + TPP * u + sub;
             int ti, tj;
             tile_rc(t, ti, tj);
-            const int gr = kT * ti + r, gc = kT * tj + c;
-            if (gr < k && gc < k)
-                v[u] = (gr >= gc) ? A[gr + (int64_t)gc * lda] + ((gr == gc) ? shift : 0.0) : 0.0;
-            else
-                v[u] = (gr == gc) ? 1.0 : 0.0;
+            gr[u] = kT * ti + r;
+            gc[u] = kT * tj + c;
+            const bool in = gr[u] < k && gr[u] >= gc[u];
+            v[u] = A[in ? gr[u] + (int64_t)gc[u] * lda : 0];
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
             const int t = t0 + TPP * u + sub;
-            if (t < nt) TS[t * kTW + r + kTP * c] = v[u];
+            const bool diag = gr[u] == gc[u];
+            double e;
+            if (gr[u] < k)
+                e = (gr[u] >= gc[u]) ? v[u] + (diag ? shift : 0.0) : 0.0;
+            else
+                e = diag ? 1.0 : 0.0;  // identity padding
+            if (t < nt) TS[t * kTW + r + kTP * c] = e;
         }
     }
 }
