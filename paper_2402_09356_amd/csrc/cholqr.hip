@@ -68,53 +68,63 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-// One wave factors diagonal tile b in registers (lane r holds row r); sets
-// *s_fail on failure.  Called by wave 0 only.  Step c broadcasts column c as
-// it stands (a_qc, before scaling) and updates the rows below with
-// a_rq -= (a_rc / a_cc) a_qc, so the broadcasts overlap the pivot's square
-// root instead of following it; the loop has no branch, so the scheduler can
+// One wave factors diagonal tile b (wave 0 only; sets *s_fail on failure).
+// Lane 16 g + r holds row r of the tile at columns g, g + 4, g + 8, g + 12,
+// so the rank-one update of step c touches at most four entries a lane.
+// Column c reaches the other lane groups through cbuf (64 doubles of LDS)
+// while its pivot, taken by readlane from the lane that holds it, goes
+// through the square root; each row below then takes
+// a_rq -= (a_rc / a_cc) a_qc.  The loop has no branch, so the scheduler can
 // overlap one step's updates with the next step's pivot.
-__device__ __forceinline__ void diag_tile(double *TS, int b, int k, double defl, double *inv, int *s_fail) {
+__device__ __forceinline__ void diag_tile(double *TS, int b, int k, double defl, double *inv, double *cbuf,
+                                          int *s_fail) {
     const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
     double *D = TS + (tri(b) + b) * kTW;
-    const int r = lane & 15;
-    double a[kT];
+    double a[4];
 #pragma unroll
-    for (int q = 0; q < kT; ++q) a[q] = D[r + kTP * q];
+    for (int s = 0; s < 4; ++s) a[s] = D[r + kTP * (4 * s + g)];
     const double dstart = D[r + kTP * r];  // this row's diagonal entry before the tile's steps
     int fail = 0;
     double my_inv = 0.0;  // 1 / L_rr, kept by lane r
 #pragma unroll
     for (int c = 0; c < kT; ++c) {
-        // entry (q, c) of the column sits in lane q of every row
-        double aq[kT];
+        const int gc = c & 3, sc = c >> 2;  // column c sits in a[sc] of group gc
+        cbuf[lane] = a[sc];
+        wave_sync();
+        const double xr = cbuf[16 * gc + r];  // a_rc
+        double aq[4];
 #pragma unroll
-        for (int q = c + 1; q < kT; ++q) aq[q] = row_bcast_at(a[c], q);
-        const double piv = readlane_d(a[c], c);
+        for (int s = sc; s < 4; ++s) aq[s] = cbuf[16 * gc + 4 * s + g];  // a_qc, q = 4 s + g
+        wave_sync();  // the next step's write follows these reads
+        const double piv = readlane_d(a[sc], 16 * gc + c);
         const double d0 = readlane_d(dstart, c);
-        const int gc = kT * b + c;
-        // the cases resolve by selects: padding (1), failure or dead
-        // direction (0), else sqrt(piv)
-        const double ivr = rsqrt(piv);
-        const bool pad = gc >= k;
+        const int gcol = kT * b + c;
+        // failure or dead direction: the column is zero.  A padding column
+        // (identity, untouched by the real columns) keeps its unit pivot.
         // (bitwise: no short-circuit branch in the pivot chain)
+        const double ivr = rsqrt(piv);
+        const bool pad = gcol >= k;
         const bool bad = !isfinite(piv) | ((defl == 0.0) & !(piv > kPivotLoss * d0));
-        const bool zero = bad | ((defl > 0.0) & (piv <= defl));
-        fail = (bad & !pad & (fail == 0)) ? gc + 1 : fail;
-        const double iv = pad ? 1.0 : (zero ? 0.0 : ivr);
-        const double lcc = pad ? 1.0 : (zero ? 0.0 : piv * ivr);
-        const double lrc = a[c] * iv;
+        const bool zero = (bad | ((defl > 0.0) & (piv <= defl))) & !pad;
+        fail = (bad & !pad & (fail == 0)) ? gcol + 1 : fail;
+        const double iv = zero ? 0.0 : ivr;
+        // column c of L (rows above c take values that only ever sit above
+        // the diagonal, which the store zeroes); a_cc iv = sqrt(a_cc) on the
+        // diagonal
+        const double lrc = xr * iv;
         const double t = lrc * iv;  // a_rc / a_cc (0 for a dead direction)
-        a[c] = (r == c) ? lcc : ((r > c) ? lrc : 0.0);
+        a[sc] = (g == gc) ? lrc : ((g > gc) ? a[sc] - t * aq[sc] : a[sc]);
 #pragma unroll
-        for (int q = c + 1; q < kT; ++q) a[q] -= t * aq[q];
+        for (int s = sc + 1; s < 4; ++s) a[s] -= t * aq[s];
         my_inv = (r == c) ? iv : my_inv;
     }
-    if (lane < kT) {
-        inv[r] = my_inv;
 #pragma unroll
-        for (int q = 0; q < kT; ++q) D[r + kTP * q] = (q <= r) ? a[q] : 0.0;
+    for (int s = 0; s < 4; ++s) {
+        const int q = 4 * s + g;
+        D[r + kTP * q] = (q <= r) ? a[s] : 0.0;
     }
+    if (lane < kT) inv[r] = my_inv;
     if (lane == 0 && fail) *s_fail = fail;
 }
 
@@ -167,60 +177,85 @@ __device__ __forceinline__ void trail_tiles(double *TS, int b, int count, int t0
     }
 }
 
+// Panel of step b: x L_bb^T = a for the 16 n rows below the diagonal tile
+// (groups = 4 n groups of four rows).  Lane j of each row of 16 holds column
+// j of one panel row, so column c of the solution crosses the row by DPP and
+// row j of L_bb (lj, strictly lower part) stays in registers: four panel rows
+// a wave instruction, U groups in flight per wave.  Lane j keeps its entry
+// unscaled and scales it by ivj = 1 / L_jj once its column is done, which
+// gives the same value as scaling at step j: the strictly lower row of L_bb
+// leaves it unchanged afterwards.  Each entry takes the same operations in
+// the same order as a row-by-row forward substitution.
+template <int U, int W>
+__device__ __forceinline__ void panel_rows(double *TS, int b, int groups, const double (&lj)[kT], double ivj) {
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int li = tid & 15, lg = (tid >> 4) & 3;
+#pragma unroll 1
+    for (int g0 = wave; g0 < groups; g0 += W * U) {
+        double x[U];
+        double *px[U];
+#pragma unroll
+        for (int v = 0; v < U; ++v) {
+            const int g = g0 + W * v;
+            const int row = 4 * (g < groups ? g : 0) + lg;  // row of the panel
+            px[v] = TS + (tri(b + 1 + (row >> 4)) + b) * kTW + (row & 15) + kTP * li;
+            x[v] = (g < groups) ? *px[v] : 0.0;
+        }
+        // each step issues its products, then its moves, then its updates,
+        // U apart, so no instruction waits on the one before it (the
+        // scheduler would otherwise chain the groups through one temporary)
+#pragma unroll
+        for (int c = 0; c < kT; ++c) {
+            double m[U], xc[U];
+#pragma unroll
+            for (int v = 0; v < U; ++v) m[v] = x[v] * ivj;
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int v = 0; v < U; ++v) xc[v] = row_bcast_at(m[v], c);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int v = 0; v < U; ++v) x[v] -= xc[v] * lj[c];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int v = 0; v < U; ++v)
+            if (g0 + W * v < groups) *px[v] = x[v] * ivj;
+    }
+}
+
 // Factor the tiles in TS (tile rows T); returns the failing column + 1, or 0.
 // Look-ahead: during the trailing update of step b, wave 0 updates tile
 // (b+1, b+1) first and factors it at once, while the other waves update the
 // rest, so each diagonal factorisation (a chain of sixteen dependent pivots)
 // overlaps the previous step's updates.
 template <bool LDS, int NTH>
-__device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, int *s_fail) {
+__device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl, double *inv, double *cbuf,
+                                          int *s_fail) {
     const int tid = threadIdx.x, wave = tid >> 6;
     constexpr int kW = NTH / 64;
-    if (wave == 0) diag_tile(TS, 0, k, defl, inv, s_fail);
+    if (wave == 0) diag_tile(TS, 0, k, defl, inv, cbuf, s_fail);
     __syncthreads();
     if (*s_fail) return *s_fail;
 #pragma unroll 1
     for (int b = 0; b + 1 < T; ++b) {
         const int n = T - b - 1;
-        // panel rows: x L_bb^T = a.  Lane j of each row of 16 holds column j
-        // of one panel row, so column c of the solution crosses the row by
-        // DPP and row j of L_bb stays in registers: four panel rows a wave
-        // instruction, kPanelU groups of four in flight per wave.  Lane j
-        // keeps its entry unscaled and scales it once its column is done,
-        // which gives the same value as scaling at step j: the strictly lower
-        // row of L_bb leaves it unchanged afterwards.  Each entry takes the
-        // same operations in the same order as a row-by-row forward
-        // substitution.
+        // panel rows: x L_bb^T = a (panel_rows; as many groups of four rows
+        // in flight per wave as the panel needs, up to kPanelU)
         {
-            const int li = tid & 15, lg = (tid >> 4) & 3;
+            const int li = tid & 15;
             const double *D = TS + (tri(b) + b) * kTW;
             double lj[kT];  // row li of L_bb, strictly lower part
 #pragma unroll
             for (int c = 0; c < kT; ++c) lj[c] = (c < li) ? D[li + kTP * c] : 0.0;
             const double ivj = inv[li];
             const int groups = 4 * n;
-#pragma unroll 1
-            for (int g0 = wave; g0 < groups; g0 += kW * kPanelU) {
-                double x[kPanelU];
-                double *px[kPanelU];
-#pragma unroll
-                for (int v = 0; v < kPanelU; ++v) {
-                    const int g = g0 + kW * v;
-                    const int row = 4 * (g < groups ? g : 0) + lg;  // row of the panel
-                    px[v] = TS + (tri(b + 1 + (row >> 4)) + b) * kTW + (row & 15) + kTP * li;
-                    x[v] = (g < groups) ? *px[v] : 0.0;
-                }
-#pragma unroll
-                for (int c = 0; c < kT; ++c) {
-#pragma unroll
-                    for (int v = 0; v < kPanelU; ++v) {
-                        const double xc = row_bcast_at(x[v] * ivj, c);
-                        x[v] -= xc * lj[c];
-                    }
-                }
-#pragma unroll
-                for (int v = 0; v < kPanelU; ++v)
-                    if (g0 + kW * v < groups) *px[v] = x[v] * ivj;
+            switch ((groups + kW - 1) / kW) {
+                case 1: panel_rows<1, kW>(TS, b, groups, lj, ivj); break;
+                case 2: panel_rows<2, kW>(TS, b, groups, lj, ivj); break;
+                case 3: panel_rows<3, kW>(TS, b, groups, lj, ivj); break;
+                case 4: panel_rows<4, kW>(TS, b, groups, lj, ivj); break;
+                case 5: panel_rows<5, kW>(TS, b, groups, lj, ivj); break;
+                default: panel_rows<kPanelU, kW>(TS, b, groups, lj, ivj); break;
             }
         }
         __syncthreads();
@@ -229,7 +264,7 @@ __device__ __forceinline__ int chol_tiles(double *TS, int T, int k, double defl,
             trail_tiles(TS, b, 1, 0, 1);  // tile (b+1, b+1)
             wave_sync();                  // its update, written across lanes, is read back by rows
             __threadfence_block();        // (tiles in global memory above 176 columns)
-            diag_tile(TS, b + 1, k, defl, inv, s_fail);
+            diag_tile(TS, b + 1, k, defl, inv, cbuf, s_fail);
         } else {
             trail_tiles(TS, b, count, wave, kW - 1);
         }
@@ -248,26 +283,33 @@ __device__ __forceinline__ void tile_rc(int t, int &i, int &j) {
 // NTH threads: NTH / 256 tiles a pass, a batch of passes' loads in flight
 // together.  The loads are unconditional (entries outside the lower triangle
 // of the k x k matrix read A[0]) and the selects come after the batch, so no
-// branch separates a load from the next one.
+// branch separates a load from the next one; a thread steps from one of its
+// tiles to the next (TPP <= 2 further in row-by-row order) without a root.
 template <bool LDS, int NTH>
 __device__ __forceinline__ void load_tiles(double *TS, int T, int k, const double *A, int64_t lda, double shift) {
     constexpr int TPP = NTH / 256, BATCH = 32 / TPP;
+    static_assert(TPP == 1 || TPP == 2, "one step of the tile walk covers TPP <= 2");
     const int tid = threadIdx.x;
     const int r = tid & 15, c = (tid >> 4) & 15, sub = tid >> 8;
     const int nt = tri(T);
+    const int ld = (int)lda;  // k x k with k <= a few hundred: 32-bit offsets
+    int ti, tj;
+    tile_rc(sub, ti, tj);
 #pragma unroll 1
     for (int t0 = 0; t0 < nt; t0 += BATCH * TPP) {
         double v[BATCH];
         int gr[BATCH], gc[BATCH];
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
-            const int t = t0 + TPP * u + sub;
-            int ti, tj;
-            tile_rc(t, ti, tj);
             gr[u] = kT * ti + r;
             gc[u] = kT * tj + c;
             const bool in = gr[u] < k && gr[u] >= gc[u];
-            v[u] = A[in ? gr[u] + (int64_t)gc[u] * lda : 0];
+            v[u] = A[in ? gr[u] + gc[u] * ld : 0];
+            tj += TPP;
+            if (tj > ti) {
+                tj -= ti + 1;
+                ++ti;
+            }
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
@@ -306,7 +348,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_small(const SmallDesc *__
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int T = (k + kT - 1) / kT;
     double *inv = smem + tri(lds_tiles) * kTW;
-    double *red = inv + kT;
+    double *cbuf = inv + kT;  // 64: the diagonal tile's column exchange
+    double *red = cbuf + 64;
     int *s_fail = reinterpret_cast<int *>(red + 8);
     // mode 1: shift = 11 (m k + k (k+1)) u tr(A), and an exactly-zero panel
     // deflates instead of failing; mode 2: pivots below 1e-12 of the largest
@@ -339,12 +382,12 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_small(const SmallDesc *__
     if (T <= lds_tiles) {
         load_tiles<true, NTH>(smem, T, k, d.A, d.lda, shift);
         __syncthreads();
-        fail = chol_tiles<true, NTH>(smem, T, k, defl, inv, s_fail);
+        fail = chol_tiles<true, NTH>(smem, T, k, defl, inv, cbuf, s_fail);
         if (!fail) store_r<NTH>(smem, k, d.R, d.ldr);
     } else {
         load_tiles<false, NTH>(d.X, T, k, d.A, d.lda, shift);
         __syncthreads();
-        fail = chol_tiles<false, NTH>(d.X, T, k, defl, inv, s_fail);
+        fail = chol_tiles<false, NTH>(d.X, T, k, defl, inv, cbuf, s_fail);
         if (!fail) store_r<NTH>(d.X, k, d.R, d.ldr);
     }
     if (fail) {
@@ -567,6 +610,7 @@ __global__ __launch_bounds__(kThreads) void k_potrf_block(double *A, int ld, int
     constexpr int TB = 4;  // 64 = 4 tiles
     __shared__ double ts[(TB * (TB + 1) / 2) * kTW];
     __shared__ double inv[kT];
+    __shared__ double cbuf[64];
     __shared__ int s_fail;
     if (params->status != 0) return;
     const int tid = threadIdx.x;
@@ -575,7 +619,7 @@ __global__ __launch_bounds__(kThreads) void k_potrf_block(double *A, int ld, int
     double *Ab = A + b0 + (int64_t)b0 * ld;
     load_tiles<true, kThreads>(ts, T, bs, Ab, ld, 0.0);
     __syncthreads();
-    const int fail = chol_tiles<true, kThreads>(ts, T, bs, 0.0, inv, &s_fail);
+    const int fail = chol_tiles<true, kThreads>(ts, T, bs, 0.0, inv, cbuf, &s_fail);
     if (fail) {
         if (tid == 0) set_status(params, TLR_NOT_SPD, tile, tile);
         return;
@@ -678,7 +722,7 @@ tlr_status chol_small(const SmallDesc *d_descs, int count, int max_k, int mode, 
         }
     const int tmax = (max_k + kT - 1) / kT;
     const int lds_tiles = tmax < kCholLdsTiles ? tmax : kCholLdsTiles;
-    const size_t lds = sizeof(double) * ((size_t)tri(lds_tiles) * kTW + kT + 8) + 16;
+    const size_t lds = sizeof(double) * ((size_t)tri(lds_tiles) * kTW + kT + 64 + 8) + 16;
     KTimer kt(cls, s, flops, bytes, h_descs != nullptr);
     hipLaunchKernelGGL(k_chol_small, dim3(count), dim3(kCholThreads), lds, s, d_descs, mode, params, lds_tiles);
     TLR_HIP(hipGetLastError());
