@@ -500,26 +500,36 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows(const SmallDesc *__restr
             for (int u = 0; u < 4; ++u) part[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], part[u], 0, 0, 0);
         }
         if (ns > 0) acc -= (part[0] + part[1]) + (part[2] + part[3]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Ys[col * kYP + wr + lg + 4 * q] = acc[q];
-        // diagonal block: lane li of the first row of 16 solves row wr + li
-        // left to right in registers, from the values the wave just wrote
-        wave_sync();
-        if (lg == 0) {
+        // diagonal block: x R_bb = y for the wave's 16 rows in the
+        // accumulator layout (lane li holds column li of rows lg + 4 q), so
+        // column j of the solution crosses the row by DPP while row j of
+        // R_bb (strictly upper part) stays in registers.  Lane li keeps its
+        // entry unscaled and scales it once its column is done: the same
+        // operations, in the same order, as a row-by-row substitution.
+        {
             const double *Rd = Rb + (kT * b) * kTP;  // rows 16b.. of the staged block
-            double y[kT];
+            double rj[kT];
 #pragma unroll
-            for (int j = 0; j < kT; ++j) y[j] = Ys[(kT * b + j) * kYP + wr + li];
+            for (int j = 0; j < kT; ++j) rj[j] = (j < li) ? Rd[j * kTP + li] : 0.0;
+            const double ivl = invd[li];
 #pragma unroll
             for (int j = 0; j < kT; ++j) {
-                const double x = y[j] * invd[j];
-                y[j] = x;
+                double mm[4], xc[4];
 #pragma unroll
-                for (int l = j + 1; l < kT; ++l) y[l] -= x * Rd[j * kTP + l];
+                for (int q = 0; q < 4; ++q) mm[q] = acc[q] * ivl;
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xc[q] = row_bcast_at(mm[q], j);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] -= xc[q] * rj[j];
+                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
-            for (int j = 0; j < kT; ++j) Ys[(kT * b + j) * kYP + wr + li] = y[j];
+            for (int q = 0; q < 4; ++q) acc[q] *= ivl;
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ys[col * kYP + wr + lg + 4 * q] = acc[q];
     }
     __syncthreads();
     {
@@ -578,21 +588,30 @@ __global__ __launch_bounds__(kThreads) void k_trsm_rows_wide(const SmallDesc *__
             for (int u = 0; u < 8; ++u)
                 if (s0 + u < 4 * b) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
         }
-        const double *Rd = Rb + (kT * b) * kTP;  // rows 16b.. of the staged block
+        // diagonal block as in k_trsm_rows: column j crosses the row by DPP,
+        // lane li scales its entry once its column is done
+        {
+            const double *Rd = Rb + (kT * b) * kTP;  // rows 16b.. of the staged block
+            double rj[kT];
 #pragma unroll
-        for (int j = 0; j < kT; ++j) {
-            const double rjj = Rd[j * kTP + j];
-            const double iv = (rjj != 0.0) ? 1.0 / rjj : 0.0;
-            const double rjl = Rd[j * kTP + li];
+            for (int j = 0; j < kT; ++j) rj[j] = (j < li) ? Rd[j * kTP + li] : 0.0;
+            const double rll = Rd[li * kTP + li];
+            const double ivl = (rll != 0.0) ? 1.0 / rll : 0.0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                // x_j of this lane's row: column j sits in lane j of its row of 16
-                const double x = row_bcast_at(acc[q] * iv, j);
-                if (li == j)
-                    acc[q] = x;
-                else if (li > j)
-                    acc[q] -= x * rjl;
+            for (int j = 0; j < kT; ++j) {
+                double mm[4], xc[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) mm[q] = acc[q] * ivl;
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xc[q] = row_bcast_at(mm[q], j);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] -= xc[q] * rj[j];
+                __builtin_amdgcn_sched_barrier(0);
             }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] *= ivl;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
