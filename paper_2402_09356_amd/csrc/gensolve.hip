@@ -151,7 +151,8 @@ __device__ inline double readlane_d(double v, int l) {
 
 // y <- L^-1 y for one dense lower-triangular nb x nb tile (one work-group),
 // 64 rows at a time: the diagonal block is staged in LDS and solved by one
-// wave (lane r holds y_r; the solved entry is broadcast with readlane), then
+// wave (lane r holds y_r; the solved entry, y_r times the reciprocal of the
+// diagonal entry, is broadcast with readlane), then
 // every thread updates rows below from the block's columns.
 __global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L, int nb,
                                                    double *__restrict__ yv, const DevParams *params) {
@@ -178,13 +179,14 @@ __global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L,
         __syncthreads();
         if (wave == 0) {
             double v = (lane < bs) ? yv[b0 + lane] : 0.0;
+            // the reciprocals of the diagonal, all at once, keep the divide
+            // off the dependent chain of the substitution
+            const double ivl = (lane < bs) ? 1.0 / Db[lane * 66] : 0.0;
+#pragma unroll 4
             for (int r = 0; r < bs; ++r) {
-                const double xr = readlane_d(v, r) / Db[r * 66];
+                const double xr = readlane_d(v, r) * readlane_d(ivl, r);
                 const double lr = Db[lane + 65 * r];
-                if (lane == r)
-                    v = xr;
-                else if (lane > r)
-                    v -= lr * xr;
+                v = (lane == r) ? xr : ((lane > r) ? v - lr * xr : v);
             }
             xb[lane] = (lane < bs) ? v : 0.0;  // zero past the block: the row update reads all 64
             if (lane < bs) yv[b0 + lane] = v;
