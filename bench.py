@@ -77,8 +77,15 @@ def measured_traffic(kernel: str, workload: str):
 
     if rec.get("source_sha256") != source_digest() or rec.get("workload") != workload:
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else float(k["hbm_bytes_per_launch"])
+    ks = rec.get("kernels", {})
+    if kernel in ks:
+        return float(ks[kernel]["hbm_bytes_per_launch"])
+    # a launch-timer class such as k_gemm_lds<N,N> covers the instantiations
+    # k_gemm_lds<N,N,BM,BN> the counters list apart: their dispatch-weighted mean
+    pre = kernel[:-1] + "," if kernel.endswith(">") else None
+    parts = [v for name, v in ks.items() if pre and name.startswith(pre)]
+    n = sum(v["dispatches"] for v in parts)
+    return None if n == 0 else sum(v["hbm_bytes_per_launch"] * v["dispatches"] for v in parts) / n
 
 
 def roofline(stats, workload: str, warm_stats=None):
