@@ -14,9 +14,11 @@
 // stays in L2.  k is padded to a multiple of 16 with an identity block.
 //
 // One step b of the factorisation:
-//   1. one wave factors the diagonal tile in registers (lane r holds row r;
-//      the pivot comes by readlane, each new column by DPP row broadcast);
-//   2. every row of the panel below is solved against it (one thread a row);
+//   1. one wave factors the diagonal tile in registers (four columns a lane;
+//      the pivot comes by readlane, each column reaches the other lanes
+//      through a 64-double LDS exchange);
+//   2. the panel below is solved against it, one panel row across each row
+//      of 16 lanes (the solution's columns move by DPP);
 //   3. every trailing tile (i, j), b < j <= i, takes A_ij -= L_ib L_jb^T with
 //      four v_mfma_f64_16x16x4 (one wave a tile).
 // Pivot rule: a pivot that is not finite fails; with defl == 0 (dense
@@ -407,7 +409,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_small(const SmallDesc *__
 // one block ahead.  Column block b: R[0 : 16b+16, 16b : 16b+16] is staged in
 // LDS; each wave takes its 16 x 16 block, subtracts X[:, :16b] R[:16b, block]
 // with MFMA (X from the LDS copy, where the earlier blocks were solved), and
-// solves against the diagonal block one row a lane.  A zero diagonal of R
+// solves against the diagonal block in the accumulator layout (the solution's
+// columns move across each row of 16 lanes by DPP).  A zero diagonal of R
 // (dead direction) gives a zero column.
 constexpr int kTrsmLdsK = 192;
 constexpr int kBigBatchGroups = 2048;  // eight per compute unit
