@@ -235,9 +235,23 @@ __device__ void qrcp_trunc(double *M, int ld, int k, double tol2, double *cn, do
         if (lane == 0) { red[wave] = rem; red[8 + wave] = best; ired[wave] = bj; }
         __syncthreads();
         rem = 0.0; best = -1.0; bj = c;
-        for (int w = 0; w < THREADS / 64; ++w) {
-            rem += red[w];
-            if (red[8 + w] > best || (red[8 + w] == best && ired[w] < bj)) { best = red[8 + w]; bj = ired[w]; }
+        {
+            // the waves' entries read at once, then combined in registers
+            double rv[THREADS / 64], bv[THREADS / 64];
+            int iv[THREADS / 64];
+#pragma unroll
+            for (int w = 0; w < THREADS / 64; ++w) {
+                rv[w] = red[w];
+                bv[w] = red[8 + w];
+                iv[w] = ired[w];
+            }
+#pragma unroll
+            for (int w = 0; w < THREADS / 64; ++w) {
+                rem += rv[w];
+                const bool take = bv[w] > best || (bv[w] == best && iv[w] < bj);
+                best = take ? bv[w] : best;
+                bj = take ? iv[w] : bj;
+            }
         }
         if (rem <= tol2) break;
         __syncthreads();
@@ -427,17 +441,34 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
             redi[par][wave] = bj;
         }
         __syncthreads();
-        rem = 0.0;
-        best = -1.0;
-        bj = k;
+        {
+            // all the waves' entries read at once, then combined in registers
+            // (a read inside the comparison chain would put one LDS round
+            // trip per wave on the step's critical path)
+            double rv[NW], bv[NW];
+            int iv[NW];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            rem += redv[par][w];
-            if (redv[par][NW + w] > best || (redv[par][NW + w] == best && redi[par][w] < bj)) {
-                best = redv[par][NW + w];
-                bj = redi[par][w];
+            for (int w = 0; w < NW; ++w) {
+                rv[w] = redv[par][w];
+                bv[w] = redv[par][NW + w];
+                iv[w] = redi[par][w];
+            }
+            rem = 0.0;
+            best = -1.0;
+            bj = k;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                rem += rv[w];
+                const bool take = bv[w] > best || (bv[w] == best && iv[w] < bj);
+                best = take ? bv[w] : best;
+                bj = take ? iv[w] : bj;
             }
         }
+        // every lane holds the same values: in scalar registers the branches
+        // on them below are scalar too (the owner group's column loops then
+        // run one column's code, not six behind exec masks)
+        bj = __builtin_amdgcn_readfirstlane(bj);
+        rem = readlane_d(rem, 0);
         if (rem <= tol2) break;
         // Householder vector of column bj, by the group that owns it
         if (grp == bj % G) {
