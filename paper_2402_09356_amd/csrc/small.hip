@@ -736,9 +736,10 @@ __global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict_
 // Panels B_t[b0:b0+bs, :] <- L_bb^-1 B_t[b0:b0+bs, :], one work-group per
 // (panel, chunk of 64 columns); L_bb is the diagonal block of L (ld nb).  The
 // block of L and the 64 x 64 block of B go through LDS; wave w owns columns
-// 16w..16w+15.  Four 16-row steps: the rows above are taken out with MFMA
-// (L rows x solved rows), then the 16 x 16 diagonal block is solved one
-// column per lane.  Rows past bs carry an identity diagonal (zero result).
+// 16w..16w+15.  Four 16-row steps on the transposed block: the rows above
+// are taken out with MFMA (solved rows x L rows), then the 16 x 16 diagonal
+// block is solved along the lanes of each row of 16.  Rows past bs carry an
+// identity diagonal (zero result).
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kTbP = 65;  // LDS pitch of both 64-row blocks
 
@@ -773,42 +774,52 @@ __global__ __launch_bounds__(256) void k_trsm_block(const double *__restrict__ L
     }
     __syncthreads();
     const int wc = 16 * wave;  // this wave's first column
+    // Each step works on the transpose of its 16 x 16 block (lane li holds
+    // row r0 + li of the wave's columns wc + lg + 4 q), so the substitution
+    // runs along the 16 lanes of a row: the solved entry of row j moves by
+    // DPP and row li of L's diagonal block stays in registers.  A wave reads
+    // and writes only its own columns, so the steps need no barrier.
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int r0 = 16 * s;
-        if (s > 0) {
-            // rows r0..r0+15 -= L[r0.., 0:r0] X[0:r0, cols]
-            v4d acc;
+        v4d acc;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = Xs[(r0 + lg + 4 * q) + (wc + li) * kTbP];
+        for (int q = 0; q < 4; ++q) acc[q] = Xs[(r0 + li) + (wc + lg + 4 * q) * kTbP];
+        if (s > 0) {
+            // rows r0..r0+15 -= L[r0.., 0:r0] X[0:r0, cols], as its transpose
+            // X[0:r0, cols]^T L[r0.., 0:r0]^T
             v4d part = v4d{0.0, 0.0, 0.0, 0.0};
             for (int kk = 0; kk < r0; kk += 4) {
-                const double av = Ls[(r0 + li) + (kk + lg) * kTbP];
-                const double bv = Xs[(kk + lg) + (wc + li) * kTbP];
+                const double av = Xs[(kk + lg) + (wc + li) * kTbP];
+                const double bv = Ls[(r0 + li) + (kk + lg) * kTbP];
                 part = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, part, 0, 0, 0);
             }
             acc -= part;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) Xs[(r0 + lg + 4 * q) + (wc + li) * kTbP] = acc[q];
         }
-        // diagonal block: lane li of the first row of 16 solves column wc + li
-        __syncthreads();  // the block's update, written across lanes, is read back by columns
-        if (lg == 0) {
-            double y[16];
+        // diagonal block: lane li keeps row li unscaled until its own step
+        // (the rows below leave it unchanged), then scales it
+        double lj[16];  // L[r0 + li][r0 + j], strictly lower part
 #pragma unroll
-            for (int i = 0; i < 16; ++i) y[i] = Xs[(r0 + i) + (wc + li) * kTbP];
+        for (int j = 0; j < 16; ++j) lj[j] = (j < li) ? Ls[(r0 + li) + (r0 + j) * kTbP] : 0.0;
+        const double ivl = 1.0 / Ls[(r0 + li) + (r0 + li) * kTbP];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const double xi = y[i] / Ls[(r0 + i) + (r0 + i) * kTbP];
-                y[i] = xi;
+        for (int j = 0; j < 16; ++j) {
+            double mm[4], xc[4];
 #pragma unroll
-                for (int j = i + 1; j < 16; ++j) y[j] -= Ls[(r0 + j) + (r0 + i) * kTbP] * xi;
-            }
+            for (int q = 0; q < 4; ++q) mm[q] = acc[q] * ivl;
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) Xs[(r0 + i) + (wc + li) * kTbP] = y[i];
+            for (int q = 0; q < 4; ++q) xc[q] = row_bcast_at(mm[q], j);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] -= xc[q] * lj[j];
+            __builtin_amdgcn_sched_barrier(0);
         }
-        __syncthreads();  // the solved rows are read across lanes by the next step
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xs[(r0 + li) + (wc + lg + 4 * q) * kTbP] = acc[q] * ivl;
+        wave_sync();  // the solved rows are read across the wave's lanes next
     }
+    __syncthreads();  // the write-back reads every wave's columns
     {
         // write back, lane = row
 #pragma unroll
