@@ -182,7 +182,6 @@ __global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L,
             // the reciprocals of the diagonal, all at once, keep the divide
             // off the dependent chain of the substitution
             const double ivl = (lane < bs) ? 1.0 / Db[lane * 66] : 0.0;
-#pragma unroll 4
             for (int r = 0; r < bs; ++r) {
                 const double xr = readlane_d(v, r) * readlane_d(ivl, r);
                 const double lr = Db[lane + 65 * r];
