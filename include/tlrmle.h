@@ -94,6 +94,16 @@ typedef struct {
  * workspace then holds one nb x nb pair per off-diagonal tile besides the
  * low-rank slots. */
 #define TLR_PLAN_DENSE_TILES 1u
+/* Truncation rule of every compression and recompression (Section 2's
+ * accuracy threshold tol, absolute):
+ *  - default: pivoted QR of the projected k x k factor, stopped at the first
+ *    step whose trailing Frobenius norm is <= tol.  The spectral error is
+ *    <= tol; the rank is at or a few above the singular-value count.
+ *  - TLR_PLAN_SVD_TRUNCATION: one-sided Jacobi SVD of that factor, rank =
+ *    #{singular values > tol} -- the paper's rule exactly (slower).
+ * The rule is a property of the plan; the d_ranks output of tlr_compress
+ * only reports the ranks the rule produced. */
+#define TLR_PLAN_SVD_TRUNCATION 2u
 
 typedef struct tlr_plan_s *tlr_plan;
 
@@ -170,11 +180,13 @@ tlr_status tlr_gen_tiles(tlr_plan plan, const double *d_locs, tlr_theta theta, v
 
 /* Compression (Section 2, Fig. "tlr"; Section 3's accuracy threshold):
  * every off-diagonal tile A_ij (i > j) becomes U_ij V_ij^T with
- * rank r_ij = #{singular values > tol} (absolute threshold), estimated by a
- * randomised range finder with one power step and an exact SVD of the small
- * projected matrix.  d_ranks: optional out, nt*nt int32 (row-major, entry
- * i*nt + j for i > j; other entries 0): the rank of each tile, or -1 when it
- * exceeded maxrank (then the status word is TLR_RANK_OVERFLOW). */
+ * ||A_ij - U_ij V_ij^T||_2 <= tol (absolute threshold), by a randomised range
+ * finder with one power step and the plan's truncation rule applied to the
+ * small projected matrix (see TLR_PLAN_SVD_TRUNCATION).  d_ranks: optional
+ * out, nt*nt int32 (row-major, entry i*nt + j for i > j; other entries 0):
+ * the rank of each tile, -1 when it exceeded maxrank (then the status word
+ * is TLR_RANK_OVERFLOW), -2 when it is kept dense.  Requesting d_ranks does
+ * not change the computation. */
 tlr_status tlr_compress(tlr_plan plan, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks,
                         void *stream);
 
@@ -266,6 +278,18 @@ int32_t tlr_kstats_read(tlr_kstat *out, int32_t max);
 tlr_status tlr_diag_gemm(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K, double alpha,
                          const double *d_A, int32_t lda, const double *d_B, int32_t ldb, double beta,
                          double *d_C, int32_t ldc, void *stream);
+
+/* `count` products of one shape in one batched launch, C_t = alpha op(A_t)
+ * op(B_t) + beta C_t with X_t = d_X + t * stride_x (elements): the launch the
+ * likelihood path makes for a batch of tile products, including its choice
+ * between the K-split kernel and the LDS-staged kernel for tall batches (at
+ * least 256 rows of C and 256 row blocks of 64 over the batch).
+ * count <= 65535.  Synchronises `stream`; allocates and frees a descriptor
+ * temporary (diagnostic use only). */
+tlr_status tlr_diag_gemm_strided(int32_t trans_a, int32_t trans_b, int32_t count, int32_t M, int32_t N, int32_t K,
+                                 double alpha, const double *d_A, int32_t lda, int64_t stride_a, const double *d_B,
+                                 int32_t ldb, int64_t stride_b, double beta, double *d_C, int32_t ldc,
+                                 int64_t stride_c, void *stream);
 
 /* Copy tile (i, j) of the matrix held in the workspace into d_out (nb x nb,
  * column-major): for i == j the dense diagonal tile (Sigma_jj after

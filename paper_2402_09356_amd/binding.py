@@ -70,6 +70,8 @@ _SIGNATURES = {
     "tlr_version": (ctypes.c_char_p, []),
     "tlr_diag_gemm": (I32, [I32, I32, I32, I32, I32, F64, P, I32, P, I32, F64, P, I32, P]),
     "tlr_diag_svd": (I32, [I32, I32, P, F64, P, P, P, P, P]),
+    "tlr_diag_gemm_strided": (I32, [I32, I32, I32, I32, I32, I32, F64, P, I32, I64, P, I32, I64, F64, P, I32, I64,
+                                    P]),
     "tlr_diag_tile": (I32, [P, P, I32, I32, P, ctypes.POINTER(I32), P]),
     "tlr_diag_cholqr": (I32, [I32, I32, P, P, P, P]),
     "tlr_kstats_enable": (I32, [I32]),
@@ -142,12 +144,19 @@ def apply_perm(perm: torch.Tensor, locs: torch.Tensor, z: torch.Tensor | None = 
 class Plan:
     """Owns a tlr_plan handle; workspaces are torch uint8 device tensors."""
 
-    def __init__(self, n: int, nb: int, maxrank: int = 0, precision: str = "fp64", dense_tiles: bool = False):
-        """dense_tiles: keep over-rank off-diagonal tiles dense (TLR_PLAN_DENSE_TILES)."""
+    def __init__(self, n: int, nb: int, maxrank: int = 0, precision: str = "fp64", dense_tiles: bool = False,
+                 truncation: str = "qrcp"):
+        """dense_tiles: keep over-rank off-diagonal tiles dense (TLR_PLAN_DENSE_TILES);
+        truncation: "qrcp" (pivoted QR, default) or "svd" (TLR_PLAN_SVD_TRUNCATION)."""
         L = lib()
         h = ctypes.c_void_p()
-        _check(L.tlr_plan_create(ctypes.byref(h), n, nb, maxrank, PRECISIONS[precision], 1 if dense_tiles else 0),
+        flags = (1 if dense_tiles else 0) | (2 if truncation == "svd" else 0)
+        if truncation not in ("qrcp", "svd"):
+            raise ValueError("truncation must be 'qrcp' or 'svd'")
+        _check(L.tlr_plan_create(ctypes.byref(h), n, nb, maxrank, PRECISIONS[precision], flags),
                "tlr_plan_create")
+        self.truncation = truncation
+        self.precision = precision
         self._h = h
         self.n = n
         self.nb = nb
@@ -226,6 +235,20 @@ def diag_gemm(a, b, c, alpha=1.0, beta=0.0, trans_a=False, trans_b=False):
     lda, ldb, ldc = a.shape[1], b.shape[1], c.shape[1]
     _check(lib().tlr_diag_gemm(int(trans_a), int(trans_b), M, N, K, float(alpha), _ptr(a), lda, _ptr(b), ldb,
                                float(beta), _ptr(c), ldc, _stream()), "tlr_diag_gemm")
+    return c
+
+
+def diag_gemm_strided(a, b, c, trans_a=False, trans_b=False, alpha=1.0, beta=0.0):
+    """Batched c[t] = alpha op(a[t]) op(b[t]) + beta c[t] over the leading index.
+
+    a, b, c: count x cols x rows device tensors holding column-major matrices
+    (c[t] is M x N column-major, i.e. an N x M row-major slice)."""
+    count, N, M = c.shape
+    K = a.shape[1] if not trans_a else a.shape[2]
+    _check(lib().tlr_diag_gemm_strided(int(trans_a), int(trans_b), count, M, N, K, float(alpha), _ptr(a),
+                                       a.shape[2], a.shape[1] * a.shape[2], _ptr(b), b.shape[2],
+                                       b.shape[1] * b.shape[2], float(beta), _ptr(c), M, M * N, _stream()),
+           "tlr_diag_gemm_strided")
     return c
 
 

@@ -163,6 +163,45 @@ extern "C" tlr_status tlr_diag_gemm(int32_t trans_a, int32_t trans_b, int32_t M,
     return st;
 }
 
+extern "C" tlr_status tlr_diag_gemm_strided(int32_t trans_a, int32_t trans_b, int32_t count, int32_t M, int32_t N,
+                                            int32_t K, double alpha, const double *d_A, int32_t lda, int64_t stride_a,
+                                            const double *d_B, int32_t ldb, int64_t stride_b, double beta,
+                                            double *d_C, int32_t ldc, int64_t stride_c, void *stream) {
+    if (count < 0 || count > 65535 || M < 0 || N < 0 || K < 0 || !d_C || (K > 0 && (!d_A || !d_B)))
+        return TLR_E_INVAL;
+    if (count == 0 || M == 0 || N == 0) return TLR_OK;
+    if (ldc < M || lda < (trans_a ? K : M) || ldb < (trans_b ? N : K)) return TLR_E_INVAL;
+    if (stride_a < 0 || stride_b < 0 || stride_c < (int64_t)ldc * N) return TLR_E_INVAL;
+    hipStream_t s = as_stream(stream);
+    std::vector<tlr::GemmDesc> h(count);
+    for (int t = 0; t < count; ++t) {
+        tlr::GemmDesc g{};
+        g.A = d_A + stride_a * t;
+        g.B = d_B + stride_b * t;
+        g.C = d_C + stride_c * t;
+        g.M = M;
+        g.N = N;
+        g.K = K;
+        g.lda = lda > 0 ? lda : 1;
+        g.ldb = ldb > 0 ? ldb : 1;
+        g.ldc = ldc;
+        g.alpha = alpha;
+        g.beta = beta;
+        h[t] = g;
+    }
+    tlr::GemmDesc *d = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&d), sizeof(tlr::GemmDesc) * count, s) != hipSuccess)
+        return TLR_E_HIP;
+    tlr_status st = TLR_OK;
+    if (hipMemcpyAsync(d, h.data(), sizeof(tlr::GemmDesc) * count, hipMemcpyHostToDevice, s) != hipSuccess)
+        st = TLR_E_HIP;
+    if (st == TLR_OK) st = tlr::gemm_batched(trans_a != 0, trans_b != 0, d, count, M, N, s, h.data());
+    if (hipStreamSynchronize(s) != hipSuccess) st = TLR_E_HIP;
+    (void)hipFreeAsync(d, s);
+    (void)hipStreamSynchronize(s);
+    return st;
+}
+
 extern "C" tlr_status tlr_diag_svd(int32_t count, int32_t k, const double *d_A, double tol, double *d_S,
                                    double *d_X, int32_t *d_rank, void *d_scratch, void *stream) {
     if (count < 0 || k < 1 || k > tlr::kMaxSketch || !d_A || !d_S || !d_X || !d_rank || !d_scratch)

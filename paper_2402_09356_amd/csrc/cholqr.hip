@@ -22,8 +22,8 @@
 //   3. every trailing tile (i, j), b < j <= i, takes A_ij -= L_ib L_jb^T with
 //      four v_mfma_f64_16x16x4 (one wave a tile).
 // Pivot rule: a pivot that is not finite fails; with defl == 0 (dense
-// diagonal tiles) a pivot <= 1e-14 of its value at the start of its 16-column
-// step fails (singular to working precision); with defl > 0 a pivot <= defl
+// diagonal tiles) a pivot that is not positive fails, the rule of LAPACK's
+// dense Cholesky factorisation; with defl > 0 a pivot <= defl
 // is a dead direction whose whole column of L is zero, so the row solve
 // writes a zero column of Q there.
 #include <algorithm>
@@ -40,10 +40,6 @@ constexpr int kT = 16;
 constexpr int kTP = 17;
 constexpr int kTW = kT * kTP;
 constexpr int kCholLdsTiles = 11;
-// Plain mode (dense diagonal tiles): a pivot that keeps no more than this
-// fraction of its value at the start of its 16-column step is numerically
-// zero, i.e. the matrix is singular to working precision.
-constexpr double kPivotLoss = 1e-14;
 constexpr int kThreads = 256;
 constexpr int kPanelU = 6;  // groups of four panel rows a wave solves together
 
@@ -86,7 +82,6 @@ __device__ __forceinline__ void diag_tile(double *TS, int b, int k, double defl,
     double a[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) a[s] = D[r + kTP * (4 * s + g)];
-    const double dstart = D[r + kTP * r];  // this row's diagonal entry before the tile's steps
     int fail = 0;
     double my_inv = 0.0;  // 1 / L_rr, kept by lane r
 #pragma unroll
@@ -100,14 +95,13 @@ __device__ __forceinline__ void diag_tile(double *TS, int b, int k, double defl,
         for (int s = sc; s < 4; ++s) aq[s] = cbuf[16 * gc + 4 * s + g];  // a_qc, q = 4 s + g
         wave_sync();  // the next step's write follows these reads
         const double piv = readlane_d(a[sc], 16 * gc + c);
-        const double d0 = readlane_d(dstart, c);
         const int gcol = kT * b + c;
         // failure or dead direction: the column is zero.  A padding column
         // (identity, untouched by the real columns) keeps its unit pivot.
         // (bitwise: no short-circuit branch in the pivot chain)
         const double ivr = rsqrt(piv);
         const bool pad = gcol >= k;
-        const bool bad = !isfinite(piv) | ((defl == 0.0) & !(piv > kPivotLoss * d0));
+        const bool bad = !isfinite(piv) | ((defl == 0.0) & !(piv > 0.0));
         const bool zero = (bad | ((defl > 0.0) & (piv <= defl))) & !pad;
         fail = (bad & !pad & (fail == 0)) ? gcol + 1 : fail;
         const double iv = zero ? 0.0 : ivr;

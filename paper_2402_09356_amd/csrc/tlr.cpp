@@ -33,7 +33,8 @@ struct tlr_plan_s {
     uint32_t flags;
     size_t off_params, off_x, off_y, off_diag, off_rsig, off_rL, off_tstat, off_slots, off_yvec, off_omega,
         off_desc, off_arena, off_knu, off_dense, off_wide;
-    bool dense_ok;  // TLR_PLAN_DENSE_TILES: over-rank tiles kept dense in the wide slots
+    bool dense_ok;   // TLR_PLAN_DENSE_TILES: over-rank tiles kept dense in the wide slots
+    bool svd_trunc;  // TLR_PLAN_SVD_TRUNCATION: truncate by singular values, not pivoted QR
     size_t desc_bytes, arena_bytes, ws_bytes;
 };
 
@@ -771,6 +772,7 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->off_tstat = take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(p->ntiles, 1));
     p->off_slots = take(sizeof(double) * 2 * (size_t)nb * rcap * (size_t)p->ntiles);
     p->dense_ok = (flags & TLR_PLAN_DENSE_TILES) != 0;
+    p->svd_trunc = (flags & TLR_PLAN_SVD_TRUNCATION) != 0;
     p->off_dense = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
     p->off_wide = p->dense_ok ? take(sizeof(double) * 2 * (size_t)nb * nb * (size_t)std::max<int64_t>(p->ntiles, 1)) : 0;
     p->off_yvec = take(sizeof(double) * p->npad);
@@ -904,7 +906,7 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
             }
             TLR_PUSH(dg, c, gens);
             TLR_LAUNCH(c, gen_tiles_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), mc, s));
-            TLR_TRY(rsvd(c, jobs, tol, nullptr, 0, d_ranks != nullptr, q1_passes(p, hb.dp.sigma2, tol)));
+            TLR_TRY(rsvd(c, jobs, tol, nullptr, 0, p->svd_trunc, q1_passes(p, hb.dp.sigma2, tol)));
             Ctx::StatRead sr;
             TLR_TRY(c.read_stats(jobs, sr));
             TLR_TRY(c.sync_reset());
@@ -1152,7 +1154,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         TLR_TRY(make_dense(c, dt, ds));
                     }
                     if (!jobs.empty())
-                        TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, false, q1_passes(p, hb.dp.sigma2, tol)));
+                        TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, p->svd_trunc, q1_passes(p, hb.dp.sigma2, tol)));
                     TLR_TRY(issue_diag());
                     Ctx::StatRead sr;
                     TLR_TRY(c.read_stats(jobs, sr));

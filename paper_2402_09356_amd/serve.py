@@ -49,23 +49,39 @@ class Request:
 
 
 class WorkspacePool:
-    """Device workspaces by plan shape, under a byte budget."""
+    """Device workspaces by plan shape, under a byte budget.
+
+    Idle workspaces are kept for reuse by requests of the same shape.  When a
+    request needs a new workspace that the budget cannot hold, idle
+    workspaces of other shapes are given up, least recently used first, until
+    it fits (or none is left)."""
 
     def __init__(self, budget_bytes: int, device):
         self.budget = int(budget_bytes)
         self.device = device
-        self.free = {}
+        self.idle = []          # (key, workspace, bytes), least recently released first
         self.allocated = 0
         self.lock = threading.Lock()
+
+    @property
+    def free(self):
+        out = {}
+        for key, ws, _ in self.idle:
+            out.setdefault(key, []).append(ws)
+        return out
 
     def acquire(self, prob: Problem):
         import torch
 
         with self.lock:
-            lst = self.free.get(prob.key)
-            if lst:
-                return lst.pop()
-            need = prob.plan.ws_bytes
+            for i in range(len(self.idle) - 1, -1, -1):
+                if self.idle[i][0] == prob.key:
+                    return self.idle.pop(i)[1]
+            need = int(prob.plan.ws_bytes)
+            while self.allocated + need > self.budget and self.idle:
+                _, ws, size = self.idle.pop(0)
+                del ws
+                self.allocated -= size
             if self.allocated + need > self.budget:
                 return None
             self.allocated += need
@@ -78,7 +94,7 @@ class WorkspacePool:
 
     def release(self, prob: Problem, ws):
         with self.lock:
-            self.free.setdefault(prob.key, []).append(ws)
+            self.idle.append((prob.key, ws, int(prob.plan.ws_bytes)))
 
 
 class Server:

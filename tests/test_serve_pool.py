@@ -46,3 +46,22 @@ def test_concurrent_acquire_never_exceeds_budget():
         t.join()
     assert sum(w is not None for w in got) == 10
     assert pool.allocated == 640
+
+
+def test_idle_workspaces_of_other_shapes_are_evicted():
+    pool = WorkspacePool(budget_bytes=1000, device="cpu")
+    a, b = _prob(0, 100, 10, 600), _prob(1, 200, 20, 300)
+    wa, wb = pool.acquire(a), pool.acquire(b)
+    pool.release(a, wa)
+    pool.release(b, wb)
+    assert pool.allocated == 900
+    c = _prob(2, 300, 30, 200)                # a new shape: 900 + 200 > 1000
+    wc = pool.acquire(c)
+    assert wc is not None
+    assert pool.allocated == 500              # a (least recently released) given up
+    assert pool.acquire(b) is wb              # b's idle workspace is still there
+    d = _prob(3, 400, 40, 900)                # cannot fit while b and c are in use
+    assert pool.acquire(d) is None
+    pool.release(b, wb)
+    pool.release(c, wc)
+    assert pool.acquire(d) is not None and pool.allocated == 900
