@@ -291,6 +291,20 @@ tlr_status tlr_diag_gemm_strided(int32_t trans_a, int32_t trans_b, int32_t count
                                  int32_t ldb, int64_t stride_b, double beta, double *d_C, int32_t ldc,
                                  int64_t stride_c, void *stream);
 
+/* Attainable peaks of the two roofs the evaluation is measured against,
+ * timed with HIP events on `stream` (synchronises it).
+ * tlr_diag_peak_hbm: `reps` streaming copies d_src -> d_dst of `bytes`
+ * bytes each (16-byte aligned device buffers); *h_gbs = bytes read plus
+ * bytes written per second / 1e9.
+ * tlr_diag_peak_mfma_f64: independent v_mfma_f64_16x16x4 chains, `iters`
+ * steps on eight waves of every compute unit; *h_tflops = FP64 matrix-core
+ * flops per second / 1e12.  d_scratch receives one double per thread
+ * (scratch_words >= 512 * compute units). */
+tlr_status tlr_diag_peak_hbm(const void *d_src, void *d_dst, int64_t bytes, int32_t reps, double *h_gbs,
+                             void *stream);
+tlr_status tlr_diag_peak_mfma_f64(double *d_scratch, int64_t scratch_words, int32_t iters, double *h_tflops,
+                                  void *stream);
+
 /* Copy tile (i, j) of the matrix held in the workspace into d_out (nb x nb,
  * column-major): for i == j the dense diagonal tile (Sigma_jj after
  * tlr_gen_tiles, its Cholesky factor in the lower triangle after tlr_potrf);

@@ -70,6 +70,8 @@ _SIGNATURES = {
     "tlr_version": (ctypes.c_char_p, []),
     "tlr_diag_gemm": (I32, [I32, I32, I32, I32, I32, F64, P, I32, P, I32, F64, P, I32, P]),
     "tlr_diag_svd": (I32, [I32, I32, P, F64, P, P, P, P, P]),
+    "tlr_diag_peak_hbm": (I32, [P, P, I64, I32, ctypes.POINTER(F64), P]),
+    "tlr_diag_peak_mfma_f64": (I32, [P, I64, I32, ctypes.POINTER(F64), P]),
     "tlr_diag_gemm_strided": (I32, [I32, I32, I32, I32, I32, I32, F64, P, I32, I64, P, I32, I64, F64, P, I32, I64,
                                     P]),
     "tlr_diag_tile": (I32, [P, P, I32, I32, P, ctypes.POINTER(I32), P]),
@@ -250,6 +252,27 @@ def diag_gemm_strided(a, b, c, trans_a=False, trans_b=False, alpha=1.0, beta=0.0
                                        b.shape[1] * b.shape[2], float(beta), _ptr(c), M, M * N, _stream()),
            "tlr_diag_gemm_strided")
     return c
+
+
+def peak_hbm(gib: float = 4.0, reps: int = 10, device="cuda") -> float:
+    """Measured streaming-copy bandwidth in GB/s (read + write bytes)."""
+    nbytes = int(gib * 2**30) // 16 * 16
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=device)
+    dst = torch.empty_like(src)
+    out = F64()
+    _check(lib().tlr_diag_peak_hbm(_ptr(src), _ptr(dst), nbytes, reps, ctypes.byref(out), _stream()),
+           "tlr_diag_peak_hbm")
+    return out.value
+
+
+def peak_mfma_f64(iters: int = 20000, device="cuda") -> float:
+    """Measured FP64 matrix-core rate in TFLOP/s."""
+    cus = torch.cuda.get_device_properties(device).multi_processor_count
+    scratch = torch.empty(512 * cus, dtype=torch.float64, device=device)
+    out = F64()
+    _check(lib().tlr_diag_peak_mfma_f64(_ptr(scratch), scratch.numel(), iters, ctypes.byref(out), _stream()),
+           "tlr_diag_peak_mfma_f64")
+    return out.value
 
 
 def diag_svd(mats: torch.Tensor, tol: float):

@@ -202,6 +202,16 @@ extern "C" tlr_status tlr_diag_gemm_strided(int32_t trans_a, int32_t trans_b, in
     return st;
 }
 
+extern "C" tlr_status tlr_diag_peak_hbm(const void *d_src, void *d_dst, int64_t bytes, int32_t reps,
+                                        double *h_gbs, void *stream) {
+    return tlr::peak_hbm(d_src, d_dst, bytes, reps, h_gbs, as_stream(stream));
+}
+
+extern "C" tlr_status tlr_diag_peak_mfma_f64(double *d_scratch, int64_t scratch_words, int32_t iters,
+                                             double *h_tflops, void *stream) {
+    return tlr::peak_mfma_f64(d_scratch, scratch_words, iters, h_tflops, as_stream(stream));
+}
+
 extern "C" tlr_status tlr_diag_svd(int32_t count, int32_t k, const double *d_A, double tol, double *d_S,
                                    double *d_X, int32_t *d_rank, void *d_scratch, void *stream) {
     if (count < 0 || k < 1 || k > tlr::kMaxSketch || !d_A || !d_S || !d_X || !d_rank || !d_scratch)

@@ -40,6 +40,9 @@ struct DevParams {
     int32_t fail_i, fail_j;  // tile of first failure
     int32_t dense_ok;        // over-rank tiles are kept dense by the host: not a failure
     int32_t pad1;
+    // truncation floor relative to the operator's norm when the low-rank
+    // factors are stored in float32 (0: float64 factors, plain tol)
+    double floor_rel;
 };
 
 // First failure wins: record code and tile unless a failure is already stored.

@@ -220,8 +220,8 @@ __global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L,
 }
 
 struct GemvDesc {
-    const double *U;
-    const double *V;
+    const void *U;  // float64, or float32 in the f32 instantiation
+    const void *V;
     const double *yj;
     double *yi;
     const int32_t *r_dev;
@@ -234,10 +234,13 @@ struct GemvDesc {
 // updates its four rows of y_i from four columns of U at a time.
 constexpr int kGemvRowsPerLane = 16;  // nb <= 1024 in registers; longer tiles loop
 
+template <class T>
 __global__ __launch_bounds__(256) void k_lr_gemv(const GemvDesc *__restrict__ descs, int nb,
                                                  const DevParams *params) {
     __shared__ double t[4096];  // rank <= nb <= 4096 (a dense tile has rank nb)
     const GemvDesc d = descs[blockIdx.x];
+    const T *__restrict__ Uf = static_cast<const T *>(d.U);
+    const T *__restrict__ Vf = static_cast<const T *>(d.V);
     const int r = *d.r_dev;
     if (r <= 0 || params->status != 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -250,16 +253,23 @@ __global__ __launch_bounds__(256) void k_lr_gemv(const GemvDesc *__restrict__ de
         }
         for (int c = wave; c < r; c += 8) {
             const int c2 = c + 4;
-            const double *v1 = d.V + (int64_t)c * nb;
-            const double *v2 = d.V + (int64_t)(c2 < r ? c2 : c) * nb;
+            const T *v1 = Vf + (int64_t)c * nb;
+            const T *v2 = Vf + (int64_t)(c2 < r ? c2 : c) * nb;
             double a1 = 0.0, a2 = 0.0;
+            // every load of the two columns issued before the first use (a
+            // float32 entry is widened only at its multiply); rows past the
+            // tile read its last row, which meets yj = 0 there
+            T w1[kGemvRowsPerLane], w2[kGemvRowsPerLane];
 #pragma unroll
             for (int u = 0; u < kGemvRowsPerLane; ++u) {
-                const int q = q0 + lane + 64 * u;
-                const double w1 = (q < nb) ? v1[q] : 0.0;
-                const double w2 = (q < nb) ? v2[q] : 0.0;
-                a1 += w1 * yj[u];
-                a2 += w2 * yj[u];
+                const int q = min(q0 + lane + 64 * u, nb - 1);
+                w1[u] = v1[q];
+                w2[u] = v2[q];
+            }
+#pragma unroll
+            for (int u = 0; u < kGemvRowsPerLane; ++u) {
+                a1 += (double)w1[u] * yj[u];
+                a2 += (double)w2[u] * yj[u];
             }
             for (int off = 32; off > 0; off >>= 1) {
                 a1 += __shfl_xor(a1, off, 64);
@@ -276,24 +286,25 @@ __global__ __launch_bounds__(256) void k_lr_gemv(const GemvDesc *__restrict__ de
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         int c = 0;
         for (; c + 4 <= r; c += 4) {
-            double uv[4][4];
+            T uv[4][4];
+            // rows past the tile read its last row; their sums are never stored
 #pragma unroll
             for (int k = 0; k < 4; ++k)
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
-                    const int row = row0 + 256 * k;
-                    uv[k][w] = (row < nb) ? d.U[row + (int64_t)(c + w) * nb] : 0.0;
+                    const int row = min(row0 + 256 * k, nb - 1);
+                    uv[k][w] = Uf[row + (int64_t)(c + w) * nb];
                 }
 #pragma unroll
             for (int k = 0; k < 4; ++k)
 #pragma unroll
-                for (int w = 0; w < 4; ++w) acc[k] += uv[k][w] * t[c + w];
+                for (int w = 0; w < 4; ++w) acc[k] += (double)uv[k][w] * t[c + w];
         }
         for (; c < r; ++c)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int row = row0 + 256 * k;
-                if (row < nb) acc[k] += d.U[row + (int64_t)c * nb] * t[c];
+                if (row < nb) acc[k] += (double)Uf[row + (int64_t)c * nb] * t[c];
             }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -413,19 +424,23 @@ tlr_status trsv_tile(const double *L, int nb, double *yv, const DevParams *param
     return TLR_OK;
 }
 
-tlr_status lr_gemv(const void *d_descs, int count, int nb, const DevParams *params, hipStream_t s) {
+tlr_status lr_gemv(const void *d_descs, int count, int nb, const DevParams *params, hipStream_t s, bool f32) {
     if (count <= 0) return TLR_OK;
     static const int cls = ktimer_class("k_lr_gemv");
     KTimer kt(cls, s, 0.0, 0.0, false);  // ranks live in the descriptors on the device
-    hipLaunchKernelGGL(k_lr_gemv, dim3(count), dim3(256), 0, s, static_cast<const GemvDesc *>(d_descs), nb,
-                       params);
+    if (f32)
+        hipLaunchKernelGGL((k_lr_gemv<float>), dim3(count), dim3(256), 0, s, static_cast<const GemvDesc *>(d_descs),
+                           nb, params);
+    else
+        hipLaunchKernelGGL((k_lr_gemv<double>), dim3(count), dim3(256), 0, s, static_cast<const GemvDesc *>(d_descs),
+                           nb, params);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }
 
 size_t gemv_desc_bytes() { return sizeof(GemvDesc); }
 
-void make_gemv_desc(void *dst, const double *U, const double *V, const double *yj, double *yi,
+void make_gemv_desc(void *dst, const void *U, const void *V, const double *yj, double *yi,
                     const int32_t *r_dev) {
     GemvDesc g{U, V, yj, yi, r_dev};
     *static_cast<GemvDesc *>(dst) = g;

@@ -11,9 +11,9 @@ namespace tlr {
 // override pointer is set, the device value replaces the field (sizes that
 // are only known on the device, e.g. a rank computed by an earlier kernel).
 struct GemmDesc {
-    const double *A;
-    const double *B;
-    double *C;
+    const void *A;  // element type of A, B and C: see the `types` bits below
+    const void *B;
+    void *C;
     const int32_t *M_dev;
     const int32_t *N_dev;
     const int32_t *K_dev;
@@ -26,9 +26,12 @@ struct GemmDesc {
 // (they size the grid; products smaller than the bound exit early).
 // h_descs: optional host copy of the descriptors, used only to count the
 // launch's work for the launch timer.
+// types: which of A, B, C hold float32 (the rest float64); the arithmetic is
+// float64 in every case.  Supported: none, C, A, A+B, A+C, B+C.
+enum { kGemmA32 = 1, kGemmB32 = 2, kGemmC32 = 4 };
 tlr_status gemm_batched(bool trans_a, bool trans_b, const GemmDesc *d_descs, int count, int max_m,
                         int max_n, hipStream_t s, const GemmDesc *h_descs = nullptr,
-                        bool lower_only = false);
+                        bool lower_only = false, int types = 0);
 
 // Small dense problems, one work-group each.
 struct SmallDesc {
@@ -43,6 +46,9 @@ struct SmallDesc {
     int32_t k, lda, ldr, ldx, m, ldy;
     int32_t k_full;        // sketch width at which the sample is exact
     int32_t tile_i, tile_j;
+    // mixed precision: extra rounding-noise norm of the tile's operator (a
+    // device value added to ||A||_F in the truncation floor), or null
+    const double *noise;
 };
 
 // R = upper Cholesky factor of A (+ shift I).  mode 1: shift = 11 (m k +
@@ -64,7 +70,9 @@ tlr_status jacobi_svd(const SmallDesc *d_descs, int count, int max_k, double tol
                       int k_full, int rank_cap, DevParams *params, hipStream_t s);
 
 // Truncated Householder QR with column pivoting of A (k x k): rank r is the
-// first step whose trailing Frobenius norm is <= tol; X = Q1 (k x r),
+// first step whose trailing Frobenius norm is <= thr, where thr = tol, or
+// with params->floor_rel > 0 (factors stored in float32)
+// thr = max(tol, floor_rel (||A||_F + *noise)); X = Q1 (k x r),
 // Y = B^T (k x r) with A ~ Q1 B; R = k x k scratch (when k is too large for LDS).
 // flag = 1 (rank 0 written) when k - r < min_tail and k < k_full.
 tlr_status qrcp_trunc(const SmallDesc *d_descs, int count, int max_k, double tol, int min_tail, int k_full,
@@ -77,9 +85,10 @@ void potrf_tile_descs(double *A, int nb, GemmDesc *h);
 tlr_status potrf_tile(double *A, int nb, int tile, DevParams *params, const GemmDesc *d_desc, hipStream_t s);
 
 struct CopyDesc {
-    const double *src;
-    double *dst;
+    const void *src;
+    void *dst;
     int64_t words;
+    int32_t conv;  // 0: float64 -> float64, 1: float32 -> float64, 2: float32 -> float32
 };
 tlr_status copy_batched(const CopyDesc *d_descs, int count, int64_t max_words, hipStream_t s);
 // Each of the `count` nb x nb matrices (device pointer array) set to I.
@@ -88,11 +97,14 @@ tlr_status identity_batched(double *const *d_ptrs, int count, int nb, hipStream_
 // L lower (nb x nb).  descs: A = L (shared), Y = B_t, k = cols_t.
 // d_gemm / h_gemm: room for count * ceil(nb/64) descriptors; h_gemm ==
 // nullptr means the caller has already put them at d_gemm (see below).
+// y32: the panels hold float32 (read and written as such; float64 arithmetic).
 tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, const SmallDesc *h_descs,
-                           int count, int max_cols, GemmDesc *d_gemm, GemmDesc *h_gemm, hipStream_t s);
+                           int count, int max_cols, GemmDesc *d_gemm, GemmDesc *h_gemm, hipStream_t s,
+                           bool y32 = false);
 // The GEMM descriptors trsm_left_lower uses (ceil(nb/64) * count entries,
 // block major), for a caller that uploads them itself.
-void trsm_left_lower_descs(const double *L, int nb, const SmallDesc *h_descs, int count, GemmDesc *h_gemm);
+void trsm_left_lower_descs(const double *L, int nb, const SmallDesc *h_descs, int count, GemmDesc *h_gemm,
+                           bool y32 = false);
 
 // Matern tile generation.
 struct GenDesc {
@@ -114,14 +126,36 @@ tlr_status split_locs(const double *locs, int64_t n, int64_t npad, double *x, do
 tlr_status pad_copy(const double *z, int64_t n, int64_t npad, double *out, hipStream_t s);
 tlr_status trsv_tile(const double *L, int nb, double *yv, const DevParams *params, hipStream_t s);
 size_t gemv_desc_bytes();
-void make_gemv_desc(void *dst, const double *U, const double *V, const double *yj, double *yi,
+void make_gemv_desc(void *dst, const void *U, const void *V, const double *yj, double *yi,
                     const int32_t *r_dev);
-tlr_status lr_gemv(const void *d_descs, int count, int nb, const DevParams *params, hipStream_t s);
+// f32: U and V of every descriptor hold float32.
+tlr_status lr_gemv(const void *d_descs, int count, int nb, const DevParams *params, hipStream_t s,
+                   bool f32 = false);
+// Frobenius norms of low-rank factor panels (nb x r float32, r from the
+// device): out[t] = ||V_t||_F.  One work-group a panel.
+struct NormDesc {
+    const float *V;
+    const int32_t *r_dev;
+    double *out;
+};
+tlr_status factor_norms(const NormDesc *d_descs, int count, int nb, hipStream_t s);
+// Rounding-noise norm of the Schur complement of tile (i, j) at column j:
+// out[t] = sqrt(nrm_s[i nt + j]^2 + sum_{k<j} (nrm_l[i nt + k] nrm_l[j nt + k])^2).
+struct NoiseDesc {
+    int32_t i, j;
+    double *out;
+};
+tlr_status schur_noise(const NoiseDesc *d_descs, int count, int nt, const double *nrm_s, const double *nrm_l,
+                       hipStream_t s);
 tlr_status logdet_quad(const double *diag, int nb, int nt, int64_t n, const double *yv, const DevParams *params,
                        double *out, hipStream_t s);
 // dst[:, c] = src[:, c] for c < *cols_dev (rows x cols panels).
 tlr_status copy_panel(const double *src, int64_t lds, double *dst, int64_t ldd, int rows, const int32_t *cols_dev,
                       int max_cols, hipStream_t s);
+
+// Attainable peaks (measured): streaming copy bandwidth and FP64 MFMA rate.
+tlr_status peak_hbm(const void *src, void *dst, int64_t bytes, int reps, double *gbs, hipStream_t s);
+tlr_status peak_mfma_f64(double *scratch, int64_t scratch_words, int iters, double *tflops, hipStream_t s);
 
 // Orderings.
 size_t reorder_ws_bytes(int64_t n, tlr_ordering kind);

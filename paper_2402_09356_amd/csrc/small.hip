@@ -197,6 +197,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi_svd(const SmallDesc *_
 
 // --------------------------------------------- truncated pivoted QR --
 
+// Squared stopping threshold of the truncation: tol^2, or with float32
+// factors (floor_rel > 0) max(tol, floor_rel (||A||_F + noise))^2, where
+// ||A||_F^2 = total2 is the whole matrix's squared Frobenius norm and noise
+// the rounding-noise norm of the operator the sketch was taken of: directions
+// below that level are float32 rounding, not rank.
+__device__ inline double trunc_thr2(const DevParams *params, const double *noise, double total2, double tol2) {
+    const double rel = params->floor_rel;
+    if (!(rel > 0.0)) return tol2;
+    const double f = rel * (sqrt(total2) + (noise ? *noise : 0.0));
+    return fmax(tol2, f * f);
+}
+
 // Householder QR with column pivoting of A (k x k), stopped at the first step
 // c where the Frobenius norm of the trailing block is <= tol:
 //     A Pi = Q [R11 R12; 0 R22],  ||R22||_F <= tol,
@@ -207,7 +219,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_jacobi_svd(const SmallDesc *_
 // that the thread owning column j and its neighbours touch consecutive words.
 template <int THREADS>
 __device__ void qrcp_trunc(double *M, int ld, int k, double tol2, double *cn, double *beta, int *perm,
-                           double *red, int *ired, int *s_r) {
+                           double *red, int *ired, int *s_r, const DevParams *params, const double *noise) {
     const int tid = threadIdx.x;
     for (int j = tid; j < k; j += THREADS) {
         double s2 = 0.0;
@@ -253,6 +265,7 @@ __device__ void qrcp_trunc(double *M, int ld, int k, double tol2, double *cn, do
                 bj = take ? iv[w] : bj;
             }
         }
+        if (c == 0) tol2 = trunc_thr2(params, noise, rem, tol2);
         if (rem <= tol2) break;
         __syncthreads();
         if (bj != c) {  // swap columns c and bj (all rows), norms and permutation
@@ -376,7 +389,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
     if (k < kmin || k > KC || k > KR) return;  // another kernel's range
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = wave * 4 + (lane >> 4), sl = lane & 15;
-    const double tol2 = tol * tol;
+    double tol2 = tol * tol;
     double *__restrict__ V = d.R;
     double a[CPG][RPS];
     // per column of the group: squared norm of its rows below the current
@@ -469,6 +482,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
         // run one column's code, not six behind exec masks)
         bj = __builtin_amdgcn_readfirstlane(bj);
         rem = readlane_d(rem, 0);
+        if (c == 0) tol2 = trunc_thr2(params, d.noise, rem, tol2);
         if (rem <= tol2) break;
         // Householder vector of column bj, by the group that owns it
         if (grp == bj % G) {
@@ -666,7 +680,7 @@ __global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict_
         M[i * ldm + j] = d.A[i + (int64_t)j * d.lda];
     }
     __syncthreads();
-    qrcp_trunc<256>(M, ldm, k, tol * tol, cn, beta, perm, red, ired, &s_r);
+    qrcp_trunc<256>(M, ldm, k, tol * tol, cn, beta, perm, red, ired, &s_r, params, d.noise);
     // a rank within min_tail of the sample width means the sample was too
     // narrow: keep the previous factors (rank 0 written) and let the host retry
     const int insufficient = (k - s_r < min_tail) && (k < (d.k_full < k_full ? d.k_full : k_full));
@@ -743,11 +757,13 @@ __global__ __launch_bounds__(256) void k_qrcp_trunc(const SmallDesc *__restrict_
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kTbP = 65;  // LDS pitch of both 64-row blocks
 
+template <class T>
 __global__ __launch_bounds__(256) void k_trsm_block(const double *__restrict__ L, int ldl, int b0, int bs,
                                                      const SmallDesc *__restrict__ descs) {
     __shared__ double Ls[64 * kTbP];  // Ls[r + c * kTbP] = L[b0 + r][b0 + c]
     __shared__ double Xs[64 * kTbP];  // Xs[r + c * kTbP]: row r, column c of the block of B
     const SmallDesc d = descs[blockIdx.y];
+    T *__restrict__ Y = reinterpret_cast<T *>(d.Y);
     const int cols = d.k_dev ? *d.k_dev : d.k;
     const int c0 = blockIdx.x * 64;
     if (c0 >= cols) return;
@@ -767,7 +783,7 @@ __global__ __launch_bounds__(256) void k_trsm_block(const double *__restrict__ L
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int c = 4 * u + wave, col = c0 + c;
-            v[u] = (lane < bs && col < cols) ? d.Y[(int64_t)col * d.ldy + b0 + lane] : 0.0;
+            v[u] = (lane < bs && col < cols) ? (double)Y[(int64_t)col * d.ldy + b0 + lane] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) Xs[lane + (4 * u + wave) * kTbP] = v[u];
@@ -825,7 +841,7 @@ __global__ __launch_bounds__(256) void k_trsm_block(const double *__restrict__ L
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int c = 4 * u + wave, col = c0 + c;
-            if (lane < bs && col < cols) d.Y[(int64_t)col * d.ldy + b0 + lane] = Xs[lane + c * kTbP];
+            if (lane < bs && col < cols) Y[(int64_t)col * d.ldy + b0 + lane] = (T)Xs[lane + c * kTbP];
         }
     }
 }
@@ -893,11 +909,80 @@ void potrf_tile_descs(double *A, int nb, GemmDesc *h) {
 namespace {
 __global__ void k_copy_batched(const CopyDesc *__restrict__ descs) {
     const CopyDesc d = descs[blockIdx.y];
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d.words;
-         e += (int64_t)gridDim.x * blockDim.x)
-        d.dst[e] = d.src[e];
+    double *__restrict__ dst = static_cast<double *>(d.dst);
+    if (d.conv == 1) {
+        const float *__restrict__ src = static_cast<const float *>(d.src);
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d.words;
+             e += (int64_t)gridDim.x * blockDim.x)
+            dst[e] = (double)src[e];
+    } else if (d.conv == 2) {
+        const float *__restrict__ src = static_cast<const float *>(d.src);
+        float *__restrict__ fdst = static_cast<float *>(d.dst);
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d.words;
+             e += (int64_t)gridDim.x * blockDim.x)
+            fdst[e] = src[e];
+    } else {
+        const double *__restrict__ src = static_cast<const double *>(d.src);
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d.words;
+             e += (int64_t)gridDim.x * blockDim.x)
+            dst[e] = src[e];
+    }
+}
+
+// ||V||_F of an nb x r float32 panel, one work-group a panel; partial sums
+// combined in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_factor_norms(const NormDesc *__restrict__ descs, int nb) {
+    __shared__ double part[256];
+    const NormDesc d = descs[blockIdx.x];
+    const int r = d.r_dev ? *d.r_dev : 0;
+    const int64_t words = (int64_t)nb * (r > 0 ? r : 0);
+    double acc = 0.0;
+    for (int64_t e = threadIdx.x; e < words; e += 256) {
+        const double v = (double)d.V[e];
+        acc += v * v;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *d.out = sqrt(part[0]);
+}
+
+// Rounding-noise norm of the Schur complement of tile (i, j), one thread a tile.
+__global__ __launch_bounds__(64) void k_schur_noise(const NoiseDesc *__restrict__ descs, int count, int nt,
+                                                    const double *__restrict__ nrm_s,
+                                                    const double *__restrict__ nrm_l) {
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t >= count) return;
+    const NoiseDesc d = descs[t];
+    // the terms' rounding errors are independent: their norms add in quadrature
+    const double s0 = nrm_s[(int64_t)d.i * nt + d.j];
+    double acc = s0 * s0;
+    for (int k = 0; k < d.j; ++k) {
+        const double t = nrm_l[(int64_t)d.i * nt + k] * nrm_l[(int64_t)d.j * nt + k];
+        acc += t * t;
+    }
+    *d.out = sqrt(acc);
 }
 }  // namespace
+
+tlr_status factor_norms(const NormDesc *d_descs, int count, int nb, hipStream_t s) {
+    if (count <= 0) return TLR_OK;
+    hipLaunchKernelGGL(k_factor_norms, dim3(count), dim3(256), 0, s, d_descs, nb);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status schur_noise(const NoiseDesc *d_descs, int count, int nt, const double *nrm_s, const double *nrm_l,
+                       hipStream_t s) {
+    if (count <= 0) return TLR_OK;
+    hipLaunchKernelGGL(k_schur_noise, dim3((unsigned)cdiv(count, 64)), dim3(64), 0, s, d_descs, count, nt, nrm_s,
+                       nrm_l);
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
 
 tlr_status copy_batched(const CopyDesc *d_descs, int count, int64_t max_words, hipStream_t s) {
     if (count <= 0 || max_words <= 0) return TLR_OK;
@@ -907,7 +992,8 @@ tlr_status copy_batched(const CopyDesc *d_descs, int count, int64_t max_words, h
     return TLR_OK;
 }
 
-void trsm_left_lower_descs(const double *L, int nb, const SmallDesc *h_descs, int count, GemmDesc *h_gemm) {
+void trsm_left_lower_descs(const double *L, int nb, const SmallDesc *h_descs, int count, GemmDesc *h_gemm,
+                           bool y32) {
     const int nblk = (int)cdiv(nb, 64);
     // block b, panel t: Y_t[b0+bs:, :] -= L[b0+bs:, b0:b0+bs] * Y_t[b0:b0+bs, :]
     for (int b = 0; b < nblk; ++b) {
@@ -918,9 +1004,16 @@ void trsm_left_lower_descs(const double *L, int nb, const SmallDesc *h_descs, in
             GemmDesc o{};
             o.A = L + (b0 + bs) + (int64_t)b0 * nb;
             o.lda = nb;
-            o.B = pd.Y + b0;
+            // the panel's rows b0.. and b0+bs.. in its own element type
+            if (y32) {
+                float *y = reinterpret_cast<float *>(pd.Y);
+                o.B = y + b0;
+                o.C = y + b0 + bs;
+            } else {
+                o.B = pd.Y + b0;
+                o.C = pd.Y + b0 + bs;
+            }
             o.ldb = pd.ldy;
-            o.C = pd.Y + b0 + bs;
             o.ldc = pd.ldy;
             o.M = rest;
             o.N = pd.k;
@@ -934,11 +1027,11 @@ void trsm_left_lower_descs(const double *L, int nb, const SmallDesc *h_descs, in
 }
 
 tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, const SmallDesc *h_descs,
-                           int count, int max_cols, GemmDesc *d_gemm, GemmDesc *h_gemm, hipStream_t s) {
+                           int count, int max_cols, GemmDesc *d_gemm, GemmDesc *h_gemm, hipStream_t s, bool y32) {
     if (count <= 0 || max_cols <= 0) return TLR_OK;
     const int nblk = (int)cdiv(nb, 64);
     if (h_gemm) {  // else the caller has put the descriptors on the device
-        trsm_left_lower_descs(L, nb, h_descs, count, h_gemm);
+        trsm_left_lower_descs(L, nb, h_descs, count, h_gemm, y32);
         TLR_HIP(hipMemcpyAsync(d_gemm, h_gemm, sizeof(GemmDesc) * count * nblk, hipMemcpyHostToDevice, s));
     }
     static const int cls = ktimer_class("k_trsm_block");
@@ -953,14 +1046,19 @@ tlr_status trsm_left_lower(const double *L, int nb, const SmallDesc *d_descs, co
         const int b0 = b * 64, bs = (nb - b0 < 64) ? nb - b0 : 64;
         const int rest = nb - b0 - bs;
         {
-            const double d = bs;
+            const double d = bs, wy = y32 ? 4.0 : 8.0;
             // bs^2 flops per right-hand side; the block of L once, each column read and written once
-            KTimer kt(cls, s, d * d * cols_sum, 8.0 * (d * (d + 1.0) / 2.0 + 2.0 * d * cols_sum), exact);
-            hipLaunchKernelGGL(k_trsm_block, dim3((unsigned)cdiv(max_cols, 64), count), dim3(256), 0, s, L, nb,
-                               b0, bs, d_descs);
+            KTimer kt(cls, s, d * d * cols_sum, 8.0 * d * (d + 1.0) / 2.0 + wy * 2.0 * d * cols_sum, exact);
+            if (y32)
+                hipLaunchKernelGGL((k_trsm_block<float>), dim3((unsigned)cdiv(max_cols, 64), count), dim3(256), 0, s,
+                                   L, nb, b0, bs, d_descs);
+            else
+                hipLaunchKernelGGL((k_trsm_block<double>), dim3((unsigned)cdiv(max_cols, 64), count), dim3(256), 0, s,
+                                   L, nb, b0, bs, d_descs);
         }
         if (rest > 0)
-            TLR_TRY(gemm_batched(false, false, d_gemm + (int64_t)b * count, count, rest, max_cols, s));
+            TLR_TRY(gemm_batched(false, false, d_gemm + (int64_t)b * count, count, rest, max_cols, s, nullptr, false,
+                                 y32 ? (kGemmB32 | kGemmC32) : 0));
     }
     TLR_HIP(hipGetLastError());
     return TLR_OK;

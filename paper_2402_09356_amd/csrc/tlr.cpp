@@ -32,7 +32,9 @@ struct tlr_plan_s {
     tlr_precision prec;
     uint32_t flags;
     size_t off_params, off_x, off_y, off_diag, off_rsig, off_rL, off_tstat, off_slots, off_yvec, off_omega,
-        off_desc, off_arena, off_knu, off_dense, off_wide;
+        off_desc, off_arena, off_knu, off_dense, off_wide, off_nrm_s, off_nrm_l, off_noise;
+    bool mixed;  // TLR_MIXED_FP32: low-rank factors stored in float32
+    int fw;      // bytes per stored factor entry (8, or 4 when mixed)
     bool dense_ok;   // TLR_PLAN_DENSE_TILES: over-rank tiles kept dense in the wide slots
     bool svd_trunc;  // TLR_PLAN_SVD_TRUNCATION: truncate by singular values, not pivoted QR
     size_t desc_bytes, arena_bytes, ws_bytes;
@@ -224,15 +226,22 @@ struct Ctx {
         return reinterpret_cast<double *>(ws + p->off_wide) + tile_index(i, j) * 2 * (int64_t)p->nb * p->nb;
     }
     double *wideV(int i, int j) const { return wideU(i, j) + (int64_t)p->nb * p->nb; }
-    double *U(int i, int j) const {
+    // low-rank factors of tile (i, j): float64, or float32 in a mixed plan
+    // (fac_types() gives the GEMM type bits of such an operand)
+    void *U(int i, int j) const {
         if (dense(i, j)) return wideU(i, j);
-        return reinterpret_cast<double *>(ws + p->off_slots) + tile_index(i, j) * 2 * (int64_t)p->nb * p->rcap;
+        return ws + p->off_slots + (tile_index(i, j) * 2 * (int64_t)p->nb * p->rcap) * p->fw;
     }
-    double *V(int i, int j) const {
+    void *V(int i, int j) const {
         if (dense(i, j)) return wideV(i, j);
-        return reinterpret_cast<double *>(ws + p->off_slots) + tile_index(i, j) * 2 * (int64_t)p->nb * p->rcap +
-               (int64_t)p->nb * p->rcap;
+        return ws + p->off_slots + (tile_index(i, j) * 2 * (int64_t)p->nb * p->rcap + (int64_t)p->nb * p->rcap) * p->fw;
     }
+    int fa() const { return p->mixed ? kGemmA32 : 0; }   // factor as left operand
+    int fb() const { return p->mixed ? kGemmB32 : 0; }   // factor as right operand
+    int fc() const { return p->mixed ? kGemmC32 : 0; }   // factor as result
+    double *nrm_s() const { return reinterpret_cast<double *>(ws + p->off_nrm_s); }
+    double *nrm_l() const { return reinterpret_cast<double *>(ws + p->off_nrm_l); }
+    double *noise(int64_t t) const { return reinterpret_cast<double *>(ws + p->off_noise) + t; }
     tlr_status load_dense() {
         dflag.assign((size_t)p->nt * p->nt, 0);
         TLR_HIP(hipMemcpyAsync(dflag.data(), ddense(), sizeof(int32_t) * dflag.size(), hipMemcpyDeviceToHost, s));
@@ -271,6 +280,11 @@ struct Ctx {
     template <class T>
     T *push(const std::vector<T> &v) {
         return push(v.data(), v.size());
+    }
+    // a panel of `elems` factor entries (float64, or float32 in a mixed plan)
+    void *alloc_fac(size_t elems) { return alloc((elems * p->fw + 7) / 8); }
+    void *fac_at(const void *base, size_t elems) const {
+        return const_cast<char *>(static_cast<const char *>(base)) + elems * p->fw;
     }
     double *alloc(size_t words) {
         const size_t bytes = align_up(std::max<size_t>(words, 1) * sizeof(double), 256);
@@ -343,7 +357,7 @@ struct Ctx {
         if (!(ptr)) return TLR_E_NOMEM;                  \
     } while (0)
 
-GemmDesc gd(const double *A, int lda, const double *B, int ldb, double *C, int ldc, int M, int N, int K,
+GemmDesc gd(const void *A, int lda, const void *B, int ldb, void *C, int ldc, int M, int N, int K,
             double alpha, double beta) {
     GemmDesc g{};
     g.A = A;
@@ -360,7 +374,7 @@ GemmDesc gd(const double *A, int lda, const double *B, int ldb, double *C, int l
     return g;
 }
 
-tlr_status launch_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v) {
+tlr_status launch_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v, int types = 0) {
     if (v.empty()) return TLR_OK;
     int mm = 0, mn = 0;
     for (const auto &g : v) {
@@ -372,7 +386,7 @@ tlr_status launch_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v
         const size_t cnt = std::min<size_t>(65535, v.size() - off);
         auto *d = c.push(v.data() + off, cnt);
         if (!d) return TLR_E_NOMEM;
-        TLR_LAUNCH(c, gemm_batched(ta, tb, d, (int)cnt, mm, mn, c.s, v.data() + off));
+        TLR_LAUNCH(c, gemm_batched(ta, tb, d, (int)cnt, mm, mn, c.s, v.data() + off, false, types));
     }
     return TLR_OK;
 }
@@ -385,10 +399,11 @@ struct StagedGemm {
     int count = 0, mm = 0, mn = 0;
     bool ta = false, tb = false;
     bool lower = false;  // only the lower triangle of each product is needed
+    int types = 0;       // float32 operands (kGemm*32 bits)
 };
 
 tlr_status stage_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v, StagedGemm *out,
-                       bool lower = false) {
+                       bool lower = false, int types = 0) {
     *out = StagedGemm{};
     if (v.empty()) return TLR_OK;
     if (v.size() > 65535) return TLR_E_UNSUPPORTED;
@@ -399,13 +414,13 @@ tlr_status stage_gemms(Ctx &c, bool ta, bool tb, const std::vector<GemmDesc> &v,
     }
     auto *d = c.push(v.data(), v.size());
     if (!d) return TLR_E_NOMEM;
-    *out = StagedGemm{d, v.data(), (int)v.size(), mm, mn, ta, tb, lower};
+    *out = StagedGemm{d, v.data(), (int)v.size(), mm, mn, ta, tb, lower, types};
     return TLR_OK;
 }
 
 tlr_status launch_staged(Ctx &c, const StagedGemm &g) {
     if (g.count == 0 || g.mm <= 0 || g.mn <= 0) return TLR_OK;
-    TLR_LAUNCH(c, gemm_batched(g.ta, g.tb, g.d, g.count, g.mm, g.mn, c.s, g.h, g.lower));
+    TLR_LAUNCH(c, gemm_batched(g.ta, g.tb, g.d, g.count, g.mm, g.mn, c.s, g.h, g.lower, g.types));
     return TLR_OK;
 }
 
@@ -414,11 +429,12 @@ struct Job {
     int i, j, k, kfull;
     // operator: dense tile A, or the Schur form U V^T - Xi Yj^T
     const double *A = nullptr;
-    const double *Uop = nullptr, *Vop = nullptr;
+    const void *Uop = nullptr, *Vop = nullptr;  // stored factors (float32 in a mixed plan)
     int r = 0;
-    const double *Xi = nullptr;
+    const void *Xi = nullptr;  // Schur panel X_i (factor element type)
     // outputs
-    double *Uout = nullptr, *Vout = nullptr;
+    void *Uout = nullptr, *Vout = nullptr;
+    const double *noise = nullptr;  // rounding-noise norm of the operator (mixed plans)
     int32_t *stat = nullptr;
     // buffers
     double *Yb = nullptr, *Zb = nullptr, *G = nullptr, *T = nullptr, *Rt = nullptr, *Xs = nullptr, *S = nullptr,
@@ -457,9 +473,9 @@ bool alloc_job(Ctx &c, Job &jb, int R) {
 
 // out_t = op_t(in_t) (trans: op^T).  in_t == nullptr means the test matrix.
 tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega, bool into_z,
-                    const double *Yj, int Rj) {
+                    const void *Yj, int Rj) {
     const int nb = c.p->nb;
-    std::vector<GemmDesc> g1, g2, g3;
+    std::vector<GemmDesc> g1, g2, g3;  // factors and Schur panels share one element type
     const bool dense = jobs.front().A != nullptr;
     // Yj^T W is the same for every job of the column (W is one matrix, a job
     // of width k reads its first k columns): form it once, at the widest
@@ -478,23 +494,23 @@ tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega,
             g1.push_back(gd(jb.A, nb, in, nb, out, nb, nb, jb.k, nb, 1.0, 0.0));
         } else {
             // H = (trans ? U : V)^T in ; F = (trans ? Xi : Yj)^T in
-            const double *left = trans ? jb.Uop : jb.Vop;
-            const double *big = trans ? jb.Xi : Yj;
+            const void *left = trans ? jb.Uop : jb.Vop;
+            const void *big = trans ? jb.Xi : Yj;
             double *F = shared_f ? shared_f->F : jb.F;
             g1.push_back(gd(left, nb, in, nb, jb.H, std::max(jb.r, 1), jb.r, jb.k, nb, 1.0, 0.0));
             if (!shared_f) g1.push_back(gd(big, nb, in, nb, F, std::max(Rj, 1), Rj, jb.k, nb, 1.0, 0.0));
             // out = (trans ? V : U) H ; out -= (trans ? Yj : Xi) F
-            const double *right = trans ? jb.Vop : jb.Uop;
-            const double *big2 = trans ? Yj : jb.Xi;
+            const void *right = trans ? jb.Vop : jb.Uop;
+            const void *big2 = trans ? Yj : jb.Xi;
             g2.push_back(gd(right, nb, jb.H, std::max(jb.r, 1), out, nb, nb, jb.k, jb.r, 1.0, 0.0));
             g3.push_back(gd(big2, nb, F, std::max(Rj, 1), out, nb, nb, jb.k, Rj, -1.0, 1.0));
         }
     }
     if (dense) return launch_gemms(c, trans, false, g1);
     StagedGemm s1, s2, s3;
-    TLR_TRY(stage_gemms(c, true, false, g1, &s1));
-    TLR_TRY(stage_gemms(c, false, false, g2, &s2));
-    TLR_TRY(stage_gemms(c, false, false, g3, &s3));
+    TLR_TRY(stage_gemms(c, true, false, g1, &s1, false, c.fa()));
+    TLR_TRY(stage_gemms(c, false, false, g2, &s2, false, c.fa()));
+    TLR_TRY(stage_gemms(c, false, false, g3, &s3, false, c.fa()));
     TLR_TRY(launch_staged(c, s1));
     TLR_TRY(launch_staged(c, s2));
     return launch_staged(c, s3);
@@ -587,7 +603,7 @@ int q1_passes(const tlr_plan_s *p, double sigma2, double tol) {
     return tol >= 1e-12 * (double)p->nb * sigma2 ? 2 : 3;
 }
 
-tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, int Rj, bool exact_svd,
+tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int Rj, bool exact_svd,
                 int passes_q1) {
     if (jobs.empty()) return TLR_OK;
     // widest sample first: its work-groups, the longest, are dispatched
@@ -621,6 +637,7 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, in
             d.k_full = jb.kfull;
             d.tile_i = jb.i;
             d.tile_j = jb.j;
+            d.noise = jb.noise;
             sq.push_back(d);
         }
         TLR_PUSH(dsq, c, sq);
@@ -634,8 +651,8 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, in
             v.N_dev = jb.stat;
             gv2.push_back(v);
         }
-        TLR_TRY(launch_gemms(c, false, false, gu2));
-        return launch_gemms(c, false, false, gv2);
+        TLR_TRY(launch_gemms(c, false, false, gu2, c.fc()));
+        return launch_gemms(c, false, false, gv2, c.fc());
     }
     std::vector<SmallDesc> sd;
     for (auto &jb : jobs) {
@@ -669,9 +686,9 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const double *Yj, in
         v.N_dev = jb.stat;
         gv.push_back(v);
     }
-    TLR_TRY(launch_gemms(c, false, false, gu));
+    TLR_TRY(launch_gemms(c, false, false, gu, c.fc()));
     TLR_TRY(launch_gemms(c, true, false, gp));
-    TLR_TRY(launch_gemms(c, false, false, gv));
+    TLR_TRY(launch_gemms(c, false, false, gv, c.fc()));
     return TLR_OK;
 }
 
@@ -684,7 +701,7 @@ tlr_status make_dense(Ctx &c, const std::vector<std::pair<int, int>> &tiles, con
     std::vector<double *> ids;
     for (size_t q = 0; q < tiles.size(); ++q) {
         const int i = tiles[q].first, j = tiles[q].second;
-        cps.push_back(CopyDesc{src[q], c.wideU(i, j), (int64_t)nb * nb});
+        cps.push_back(CopyDesc{src[q], c.wideU(i, j), (int64_t)nb * nb, 0});
         ids.push_back(c.wideV(i, j));
         c.dflag[(size_t)i * c.p->nt + j] = 1;
     }
@@ -741,7 +758,10 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     *out = nullptr;
     if (n < 1 || nb < 16 || nb > 4096) return TLR_E_INVAL;
     if (prec != TLR_FP64 && prec != TLR_MIXED_FP32) return TLR_E_INVAL;
-    if (prec != TLR_FP64) return TLR_E_UNSUPPORTED;
+    // float32 factors: the pivoted-QR truncation with its rounding floor only
+    // (no dense off-diagonal tiles, no singular-value truncation)
+    if (prec == TLR_MIXED_FP32 && (flags & (TLR_PLAN_DENSE_TILES | TLR_PLAN_SVD_TRUNCATION)))
+        return TLR_E_UNSUPPORTED;
     auto *p = new tlr_plan_s{};
     p->n = n;
     p->nb = nb;
@@ -757,6 +777,8 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->kmax = std::min({nb, rcap + p->pover, kMaxSketch});
     p->prec = prec;
     p->flags = flags;
+    p->mixed = prec == TLR_MIXED_FP32;
+    p->fw = p->mixed ? (int)sizeof(float) : (int)sizeof(double);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -770,7 +792,10 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->off_rsig = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
     p->off_rL = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
     p->off_tstat = take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(p->ntiles, 1));
-    p->off_slots = take(sizeof(double) * 2 * (size_t)nb * rcap * (size_t)p->ntiles);
+    p->off_slots = take((size_t)p->fw * 2 * (size_t)nb * rcap * (size_t)p->ntiles);
+    p->off_nrm_s = take(sizeof(double) * (size_t)p->nt * p->nt);
+    p->off_nrm_l = take(sizeof(double) * (size_t)p->nt * p->nt);
+    p->off_noise = take(sizeof(double) * (size_t)std::max<int64_t>(p->ntiles, 1));
     p->dense_ok = (flags & TLR_PLAN_DENSE_TILES) != 0;
     p->svd_trunc = (flags & TLR_PLAN_SVD_TRUNCATION) != 0;
     p->off_dense = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
@@ -830,6 +855,9 @@ tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws,
     hb.dp.status = 0;
     hb.dp.fail_i = hb.dp.fail_j = -1;
     hb.dp.dense_ok = p->dense_ok ? 1 : 0;
+    // float32 factors carry rounding noise of about 2^-24 of their norm: the
+    // truncation floor is twice that (the sum of the two factors' roundings)
+    hb.dp.floor_rel = p->mixed ? 2.0 * 0x1.0p-24 : 0.0;
     hb.mc = mc;
     hb.hint_magic = keep_magic;
     TLR_HIP(hipMemcpyAsync(c.pblock(), &hb, sizeof(ParamsBlock), hipMemcpyHostToDevice, s));
@@ -946,6 +974,17 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
         }
         pending.swap(retry);
     }
+    if (p->mixed && p->ntiles > 0) {
+        // ||V_ij||_F = ||U_ij V_ij^T||_F (U has orthonormal columns): the
+        // scale of each stored tile's float32 rounding
+        std::vector<NormDesc> nd;
+        for (int i = 1; i < nt; ++i)
+            for (int j = 0; j < i; ++j)
+                nd.push_back(NormDesc{static_cast<const float *>(c.V(i, j)), c.tstat(tile_index(i, j)),
+                                      c.nrm_s() + (size_t)i * nt + j});
+        TLR_PUSH(dnd, c, nd);
+        TLR_LAUNCH(c, factor_norms(dnd, (int)nd.size(), nb, s));
+    }
     TLR_TRY(c.store_dense());
     TLR_HIP(hipMemcpyAsync(c.rsig(), ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
     TLR_HIP(hipMemcpyAsync(c.rL(), ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
@@ -991,11 +1030,12 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             off[k] = Rj;
             Rj += r[(size_t)j * nt + k];
         }
-        double *Yj = nullptr;
+        void *Yj = nullptr;
         if (Rj > 0) {
             // Yj = [U_j0 | ... | U_j,j-1]; Xd = [U_jk (V_jk^T V_jk)]_k; D_j -= Xd Yj^T
-            Yj = c.alloc((size_t)nb * Rj);
-            double *Xd = c.alloc((size_t)nb * Rj);
+            // (both panels in the factors' element type)
+            Yj = c.alloc_fac((size_t)nb * Rj);
+            void *Xd = c.alloc_fac((size_t)nb * Rj);
             size_t msz = 0;
             for (int k = 0; k < j; ++k) msz += (size_t)r[(size_t)j * nt + k] * r[(size_t)j * nt + k];
             double *Md = c.alloc(std::max<size_t>(msz, 1));
@@ -1007,24 +1047,24 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                 const int rk = r[(size_t)j * nt + k];
                 if (rk == 0) continue;
                 gm.push_back(gd(c.V(j, k), nb, c.V(j, k), nb, Md + mo, rk, rk, rk, nb, 1.0, 0.0));
-                gx.push_back(gd(c.U(j, k), nb, Md + mo, rk, Xd + (size_t)off[k] * nb, nb, nb, rk, rk, 1.0, 0.0));
+                gx.push_back(gd(c.U(j, k), nb, Md + mo, rk, c.fac_at(Xd, (size_t)off[k] * nb), nb, nb, rk, rk, 1.0, 0.0));
                 mo += (size_t)rk * rk;
             }
-            TLR_TRY(launch_gemms(c, true, false, gm));
-            TLR_TRY(launch_gemms(c, false, false, gx));
+            TLR_TRY(launch_gemms(c, true, false, gm, c.fa() | c.fb()));
+            TLR_TRY(launch_gemms(c, false, false, gx, c.fa() | c.fc()));
             // gather Yj: U_jk occupies the first r_jk columns of its slot (ld nb)
             std::vector<CopyDesc> cps;
             int64_t mxw = 0;
             for (int k = 0; k < j; ++k) {
                 const int rk = r[(size_t)j * nt + k];
                 if (rk == 0) continue;
-                cps.push_back(CopyDesc{c.U(j, k), Yj + (size_t)off[k] * nb, (int64_t)rk * nb});
+                cps.push_back(CopyDesc{c.U(j, k), c.fac_at(Yj, (size_t)off[k] * nb), (int64_t)rk * nb, p->mixed ? 2 : 0});
                 mxw = std::max<int64_t>(mxw, (int64_t)rk * nb);
             }
             TLR_PUSH(dcp, c, cps);
             TLR_LAUNCH(c, copy_batched(dcp, (int)cps.size(), mxw, s));
             std::vector<GemmDesc> gdg{gd(Xd, nb, Yj, nb, c.diag(j), nb, nb, nb, Rj, -1.0, 1.0)};
-            TLR_TRY(launch_gemms(c, false, true, gdg));
+            TLR_TRY(launch_gemms(c, false, true, gdg, c.fa() | c.fb()));
         }
         // dense Cholesky of the updated diagonal tile, beside the
         // recompression of the tiles below (which never reads it); only the
@@ -1089,7 +1129,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         jb.r = rij;
                         jb.Uop = c.U(i, j);
                         jb.Vop = c.V(i, j);
-                        double *Xi = c.alloc((size_t)nb * Rj);
+                        void *Xi = c.alloc_fac((size_t)nb * Rj);
                         if (!Xi) return TLR_E_NOMEM;
                         jb.Xi = Xi;
                         jb.stat = c.tstat(tile_index(i, j));
@@ -1119,11 +1159,12 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                             if (rjk == 0) continue;
                             if (rik == 0) {
                                 // zero block of X_i
-                                gxx.push_back(gd(c.U(i, k), nb, Mik, 1, Xi + (size_t)off[k] * nb, nb, nb, rjk, 0, 1.0, 0.0));
+                                gxx.push_back(gd(c.U(i, k), nb, Mik, 1, c.fac_at(Xi, (size_t)off[k] * nb), nb, nb, rjk, 0,
+                                                 1.0, 0.0));
                                 continue;
                             }
                             gmm.push_back(gd(c.V(i, k), nb, c.V(j, k), nb, Mik + mo, rik, rik, rjk, nb, 1.0, 0.0));
-                            gxx.push_back(gd(c.U(i, k), nb, Mik + mo, rik, Xi + (size_t)off[k] * nb, nb, nb, rjk, rik,
+                            gxx.push_back(gd(c.U(i, k), nb, Mik + mo, rik, c.fac_at(Xi, (size_t)off[k] * nb), nb, nb, rjk, rik,
                                              1.0, 0.0));
                             mo += (size_t)rik * rjk;
                         }
@@ -1131,8 +1172,8 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         ++pos;
                         if (jobs.size() + djobs.size() >= (size_t)kMaxWave) break;
                     }
-                    TLR_TRY(launch_gemms(c, true, false, gmm));
-                    TLR_TRY(launch_gemms(c, false, false, gxx));
+                    TLR_TRY(launch_gemms(c, true, false, gmm, c.fa() | c.fb()));
+                    TLR_TRY(launch_gemms(c, false, false, gxx, c.fa() | c.fc()));
                     // explicit Schur complement D = U V^T - X_i Y_j^T of a tile (dense or converting)
                     auto schur_dense = [&](const std::vector<Job> &js) -> tlr_status {
                         std::vector<GemmDesc> g1, g2;
@@ -1140,8 +1181,8 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                             g1.push_back(gd(jb.Uop, nb, jb.Vop, nb, jb.D, nb, nb, nb, jb.r, 1.0, 0.0));
                             g2.push_back(gd(jb.Xi, nb, Yj, nb, jb.D, nb, nb, nb, Rj, -1.0, 1.0));
                         }
-                        TLR_TRY(launch_gemms(c, false, true, g1));
-                        return launch_gemms(c, false, true, g2);
+                        TLR_TRY(launch_gemms(c, false, true, g1, c.fa() | c.fb()));
+                        return launch_gemms(c, false, true, g2, c.fa() | c.fb());
                     };
                     if (!djobs.empty()) {
                         TLR_TRY(schur_dense(djobs));
@@ -1152,6 +1193,16 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                             ds.push_back(jb.D);
                         }
                         TLR_TRY(make_dense(c, dt, ds));
+                    }
+                    if (!jobs.empty() && p->mixed) {
+                        // float32 rounding noise of each Schur operator, for the truncation floor
+                        std::vector<NoiseDesc> nz;
+                        for (Job &jb : jobs) {
+                            jb.noise = c.noise(tile_index(jb.i, jb.j));
+                            nz.push_back(NoiseDesc{jb.i, jb.j, c.noise(tile_index(jb.i, jb.j))});
+                        }
+                        TLR_PUSH(dnz, c, nz);
+                        TLR_LAUNCH(c, schur_noise(dnz, (int)nz.size(), nt, c.nrm_s(), c.nrm_l(), s));
                     }
                     if (!jobs.empty())
                         TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, p->svd_trunc, q1_passes(p, hb.dp.sigma2, tol)));
@@ -1191,8 +1242,8 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                             const int rk = st[4 * q];
                             r[(size_t)jb.i * nt + j] = rk;
                             if (p->dense_ok && rk > 0) {
-                                keep.push_back(CopyDesc{jb.Uout, c.U(jb.i, j), (int64_t)nb * rk});
-                                keep.push_back(CopyDesc{jb.Vout, c.V(jb.i, j), (int64_t)nb * rk});
+                                keep.push_back(CopyDesc{jb.Uout, c.U(jb.i, j), (int64_t)nb * rk, 0});
+                                keep.push_back(CopyDesc{jb.Vout, c.V(jb.i, j), (int64_t)nb * rk, 0});
                                 keep_max = std::max<int64_t>(keep_max, (int64_t)nb * rk);
                             }
                         }
@@ -1228,7 +1279,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             const int rij = r[(size_t)i * nt + j];
             if (rij <= 0) continue;
             SmallDesc d{};
-            d.Y = c.V(i, j);
+            d.Y = static_cast<double *>(c.V(i, j));  // float32 data in a mixed plan (y32 below)
             d.ldy = nb;
             d.k = rij;
             sd.push_back(d);
@@ -1238,10 +1289,20 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             TLR_PUSH(dsd, c, sd);
             const size_t nblk = (size_t)cdiv(nb, 64);
             if (hg.size() < sd.size() * nblk) hg.resize(sd.size() * nblk);
-            trsm_left_lower_descs(c.diag(j), nb, sd.data(), (int)sd.size(), hg.data());
+            trsm_left_lower_descs(c.diag(j), nb, sd.data(), (int)sd.size(), hg.data(), p->mixed);
             GemmDesc *dg = c.push(hg.data(), sd.size() * nblk);
             if (!dg) return TLR_E_NOMEM;
-            TLR_LAUNCH(c, trsm_left_lower(c.diag(j), nb, dsd, sd.data(), (int)sd.size(), maxc, dg, nullptr, s));
+            TLR_LAUNCH(c, trsm_left_lower(c.diag(j), nb, dsd, sd.data(), (int)sd.size(), maxc, dg, nullptr, s,
+                                          p->mixed));
+            if (p->mixed) {
+                // ||L_ij||_F = ||L_jj^-1 V_ij||_F for the noise of later Schur complements
+                std::vector<NormDesc> nd;
+                for (int i : rows)  // a tile of rank 0 gets norm 0
+                    nd.push_back(NormDesc{static_cast<const float *>(c.V(i, j)), c.tstat(tile_index(i, j)),
+                                          c.nrm_l() + (size_t)i * nt + j});
+                TLR_PUSH(dnd, c, nd);
+                TLR_LAUNCH(c, factor_norms(dnd, (int)nd.size(), nb, s));
+            }
         }
         // no wait here: the next column's first launches queue behind these.
         // The descriptor area is recycled here, where the side stream has
@@ -1285,7 +1346,7 @@ tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_byt
     for (int j = 0; j < nt; ++j) {
         TLR_TRY(trsv_tile(c.diag(j), nb, c.yvec() + (int64_t)j * nb, c.params(), s));
         const int count = first[j + 1] - first[j];
-        if (count > 0) TLR_LAUNCH(c, lr_gemv(dv + gb * first[j], count, nb, c.params(), s));
+        if (count > 0) TLR_LAUNCH(c, lr_gemv(dv + gb * first[j], count, nb, c.params(), s, p->mixed));
     }
     TLR_TRY(logdet_quad(c.diag(0), nb, nt, p->n, c.yvec(), c.params(), d_out, s));
     TLR_HIP(hipStreamSynchronize(s));
@@ -1358,7 +1419,7 @@ tlr_status tile_read(tlr_plan p, const void *d_ws, int i, int j, double *d_out, 
     TLR_HIP(hipStreamSynchronize(s));
     if (h_rank) *h_rank = r;
     std::vector<GemmDesc> g{gd(c.U(i, j), nb, c.V(i, j), nb, d_out, nb, nb, nb, std::max(r, 0), 1.0, 0.0)};
-    TLR_TRY(launch_gemms(c, false, true, g));
+    TLR_TRY(launch_gemms(c, false, true, g, c.fa() | c.fb()));
     TLR_HIP(hipStreamSynchronize(s));
     return TLR_OK;
 }

@@ -5,6 +5,7 @@ and the seeded input generators; nothing here touches the GPU library.
 
 Workloads (jittered m x m grid on the unit square, sigma2 = 1):
 
+* ``c1``: m = 40 (n = 1,600), nu = 1/2, beta = 0.1 -- the small smoke case;
 * ``c3``: m = 300 (n = 90,000), nu = 1/2, beta = 0.1 -- the n = 90,000 point of
   the paper's Section 5.3.1 timing study;
 * ``c2-<cell>``: m = 200 (n = 40,000), one (nu, beta) cell of the grid
@@ -42,6 +43,8 @@ C2_CELLS = [(nu, beta) for nu in (0.5, 1.5) for beta in (0.03, 0.1, 0.3)]
 
 
 def workload(name: str):
+    if name == "c1":
+        return dict(config=1, extra=0, m=40, theta=(1.0, 0.1, 0.5))
     if name == "c3":
         return dict(config=3, extra=0, m=300, theta=(1.0, 0.1, 0.5))
     if name.startswith("c2-"):

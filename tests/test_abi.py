@@ -96,3 +96,17 @@ def test_launch_timer_host_side():
     stats = B.kstats()
     assert all(s["launches"] == 0 and s["total_ms"] == 0.0 for s in stats)
     B.kstats_enable(False)
+
+
+def test_mixed_precision_plan_rules():
+    # float32 factors: smaller workspace; dense off-diagonal tiles and the
+    # singular-value truncation are not offered with them
+    p64 = B.Plan(9000, 900)
+    p32 = B.Plan(9000, 900, precision="mixed_fp32")
+    assert p32.ws_bytes < p64.ws_bytes
+    with pytest.raises(B.TlrError) as e:
+        B.Plan(9000, 900, precision="mixed_fp32", dense_tiles=True)
+    assert e.value.code == 3
+    with pytest.raises(B.TlrError) as e:
+        B.Plan(9000, 900, precision="mixed_fp32", truncation="svd")
+    assert e.value.code == 3
