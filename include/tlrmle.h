@@ -130,6 +130,22 @@ size_t tlr_reorder_ws_bytes(int64_t n, tlr_ordering kind);
 tlr_status tlr_reorder(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed,
                        uint32_t flags, int32_t *d_perm, void *d_ws, size_t ws_bytes, void *stream);
 
+/* Allocation-free tlr_reorder, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and bit-identical result as
+ * tlr_reorder, without a workspace: the ordering runs in a scratch array of
+ * fixed size that the library holds on every device it runs on, from its
+ * load to the end of the process.  Nothing is allocated or freed.
+ * n <= tlr_reorder_noalloc_max_n() (131,072 points); a larger n returns
+ * TLR_E_NOMEM before anything is enqueued.  All calls on one device share
+ * that device's scratch array: calls that overlap on one device (two host
+ * threads, or two streams without an ordering between them) race and give
+ * undefined results; serialise them.  The scratch keeps whatever the last
+ * call left; every call rewrites all it reads. */
+tlr_status tlr_reorder_noalloc(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed,
+                               uint32_t flags, int32_t *d_perm, void *stream);
+int64_t tlr_reorder_noalloc_max_n(void);
+
 /* Gather locations (n x 2 AoS) and observations by d_perm:
  * d_locs_out[k] = d_locs[d_perm[k]], d_z_out[k] = d_z[d_perm[k]].
  * With dequantize != 0 the gathered coordinates are rint(x*65535)/65535

@@ -54,6 +54,8 @@ I32, I64, U32, U64, F64, SZ = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, 
 _SIGNATURES = {
     "tlr_reorder_ws_bytes": (SZ, [I64, I32]),
     "tlr_reorder": (I32, [P, I64, I32, U64, U32, P, P, SZ, P]),
+    "tlr_reorder_noalloc": (I32, [P, I64, I32, U64, U32, P, P]),
+    "tlr_reorder_noalloc_max_n": (I64, []),
     "tlr_apply_perm": (I32, [P, I64, P, P, P, P, I32, P]),
     "tlr_plan_create": (I32, [ctypes.POINTER(P), I64, I32, I32, I32, U32]),
     "tlr_plan_destroy": (None, [P]),
@@ -131,6 +133,20 @@ def reorder(locs: torch.Tensor, kind: str, seed: int = 0) -> torch.Tensor:
     perm = torch.empty(max(n, 1), dtype=torch.int32, device=locs.device)[:n]
     _check(L.tlr_reorder(_ptr(locs), n, k, seed & (2 ** 64 - 1), 0, _ptr(perm), _ptr(ws), ws_bytes, _stream()),
            "tlr_reorder")
+    return perm
+
+
+def reorder_noalloc(locs: torch.Tensor, kind: str, seed: int = 0, perm: torch.Tensor | None = None) -> torch.Tensor:
+    """tlr_reorder without a workspace (the library's fixed device scratch).
+    `perm` (n int32, device) may be passed in, so that the call itself makes
+    no allocation on either side."""
+    if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
+        raise ValueError("locs must be an n x 2 float64 tensor")
+    n = locs.shape[0]
+    if perm is None:
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=locs.device)[:n]
+    _check(lib().tlr_reorder_noalloc(_ptr(locs), n, ORDERINGS[kind], seed & (2 ** 64 - 1), 0, _ptr(perm),
+                                     _stream()), "tlr_reorder_noalloc")
     return perm
 
 

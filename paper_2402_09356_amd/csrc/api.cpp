@@ -27,6 +27,13 @@ tlr_status tlr_reorder(const double *d_locs, int64_t n, tlr_ordering kind, uint6
     return tlr::reorder(d_locs, n, kind, seed, flags, d_perm, d_ws, ws_bytes, as_stream(stream));
 }
 
+tlr_status tlr_reorder_noalloc(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed, uint32_t flags,
+                               int32_t *d_perm, void *stream) {
+    return tlr::reorder_noalloc(d_locs, n, kind, seed, flags, d_perm, as_stream(stream));
+}
+
+int64_t tlr_reorder_noalloc_max_n(void) { return tlr::reorder_noalloc_max_n(); }
+
 tlr_status tlr_apply_perm(const int32_t *d_perm, int64_t n, const double *d_locs, const double *d_z,
                           double *d_locs_out, double *d_z_out, int32_t dequantize, void *stream) {
     return tlr::apply_perm(d_perm, n, d_locs, d_z, d_locs_out, d_z_out, dequantize, as_stream(stream));

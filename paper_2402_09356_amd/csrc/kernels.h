@@ -161,6 +161,9 @@ tlr_status peak_mfma_f64(double *scratch, int64_t scratch_words, int iters, doub
 size_t reorder_ws_bytes(int64_t n, tlr_ordering kind);
 tlr_status reorder(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed, uint32_t flags,
                    int32_t *d_perm, void *d_ws, size_t ws_bytes, hipStream_t s);
+tlr_status reorder_noalloc(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed, uint32_t flags,
+                           int32_t *d_perm, hipStream_t s);
+int64_t reorder_noalloc_max_n();
 tlr_status apply_perm(const int32_t *d_perm, int64_t n, const double *d_locs, const double *d_z,
                       double *d_locs_out, double *d_z_out, int dequant, hipStream_t s);
 

@@ -4,6 +4,7 @@
 #include "common.h"
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 namespace tlr {
@@ -336,19 +337,23 @@ int bits_for(int64_t n) {
 
 }  // namespace
 
-size_t reorder_ws_bytes(int64_t n, tlr_ordering kind) {
-    if (n <= 0) return 256;
-    const int64_t nblocks = cdiv(n, kSortTile);
-    size_t b = 256;                                  // flag
-    b += align_up(sizeof(uint32_t) * nblocks * kBuckets, 256);  // histogram
-    b += 2 * align_up(sizeof(uint64_t) * n, 256);    // keys, keys_alt
-    b += 2 * align_up(sizeof(int32_t) * n, 256);     // vals, vals_alt
-    if (kind == TLR_ORDER_KDTREE) {
-        b += 2 * align_up(sizeof(int32_t) * n, 256);              // rank_x, rank_y
-        b += 2 * align_up(sizeof(unsigned long long) * 2 * n, 256);  // seg min/max
-    }
-    return b;
+namespace {
+constexpr size_t au256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace bytes of one ordering of n points (kd: the KD-tree's extra arrays).
+constexpr size_t ws_bytes_for(int64_t n, bool kd) {
+    return n <= 0 ? 256
+                  : 256                                                                       // flag
+                        + au256(sizeof(uint32_t) * (size_t)((n + kSortTile - 1) / kSortTile) * kBuckets)  // hist
+                        + 2 * au256(sizeof(uint64_t) * (size_t)n)                             // keys, keys_alt
+                        + 2 * au256(sizeof(int32_t) * (size_t)n)                              // vals, vals_alt
+                        + (kd ? 2 * au256(sizeof(int32_t) * (size_t)n)                        // rank_x, rank_y
+                                    + 2 * au256(sizeof(unsigned long long) * 2 * (size_t)n)   // seg min/max
+                              : 0);
 }
+}  // namespace
+
+size_t reorder_ws_bytes(int64_t n, tlr_ordering kind) { return ws_bytes_for(n, kind == TLR_ORDER_KDTREE); }
 
 tlr_status reorder(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed, uint32_t flags,
                    int32_t *d_perm, void *d_ws, size_t ws_bytes, hipStream_t s) {
@@ -468,6 +473,49 @@ tlr_status apply_perm(const int32_t *d_perm, int64_t n, const double *d_locs, co
                        d_z, d_locs_out, d_z_out, dequant);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
+}
+
+// ------------------------------------------ allocation-free ordering --
+//
+// The same ordering with its workspace in a file-scope device array, for
+// callers that cannot allocate.  Each device holds its own copy of the array
+// from the library's load to the end of the process; the host reaches it only
+// through the address hipGetSymbolAddress returns on that device, taken on the
+// first call there and kept per device.
+
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 17;
+constexpr size_t kNoAllocBytes = ws_bytes_for(kNoAllocMaxN, true);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+int64_t reorder_noalloc_max_n() { return kNoAllocMaxN; }
+
+tlr_status reorder_noalloc(const double *d_locs, int64_t n, tlr_ordering kind, uint64_t seed, uint32_t flags,
+                           int32_t *d_perm, hipStream_t s) {
+    if (n < 0 || (n > 0 && (!d_locs || !d_perm))) return TLR_E_INVAL;
+    if ((int)kind < 0 || (int)kind > 4) return TLR_E_INVAL;
+    if (n > kNoAllocMaxN) return TLR_E_NOMEM;
+    if (n == 0) return TLR_OK;
+    int dev = 0;
+    TLR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return TLR_E_UNSUPPORTED;
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (!g_scratch[dev]) {
+            void *ptr = nullptr;
+            TLR_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return TLR_E_HIP;
+            g_scratch[dev] = ptr;
+        }
+        ws = g_scratch[dev];
+    }
+    return reorder(d_locs, n, kind, seed, flags, d_perm, ws, kNoAllocBytes, s);
 }
 
 }  // namespace tlr
