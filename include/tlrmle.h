@@ -106,6 +106,7 @@ typedef struct {
 #define TLR_PLAN_SVD_TRUNCATION 2u
 
 typedef struct tlr_plan_s *tlr_plan;
+typedef struct tlr_batch_plan_s *tlr_batch_plan;
 
 /* ------------------------------------------------------------------------ */
 /* Ordering (paper Section 3)                                                */
@@ -225,6 +226,36 @@ tlr_status tlr_solve_logdet(tlr_plan plan, const double *d_z, void *d_ws, size_t
 tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tlr_theta theta,
                       double tol, void *d_ws, size_t ws_bytes, double *d_out, int32_t *d_ranks,
                       void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched evaluation of independent problems                               */
+/* ------------------------------------------------------------------------ */
+
+/* One plan per problem (count >= 1; h_n[p] points, tile size h_nb[p]; the
+ * same maxrank, precision and flags for all), as tlr_plan_create.  Host-only.
+ * The batch workspace is the problems' workspaces back to back. */
+tlr_status tlr_batch_plan_create(tlr_batch_plan *out, int32_t count, const int64_t *h_n, const int32_t *h_nb,
+                                 int32_t maxrank, tlr_precision precision, uint32_t flags);
+void tlr_batch_plan_destroy(tlr_batch_plan bplan);
+size_t tlr_batch_ws_bytes(tlr_batch_plan bplan);
+
+/* l(theta_p) of every problem p of the batch: the evaluation of tlr_loglik
+ * for each (Section 1 eq. "loglik" through Sections 2-4), run on `workers`
+ * (1..16) library-owned streams of default priority, widest problems first,
+ * so that the problems' small factorisation kernels overlap on the device.
+ * h_locs, h_z: host arrays of count device pointers (ordered n_p x 2 AoS
+ * locations and n_p observations); h_theta: host array of count thetas.
+ * d_out: device, count x 3 float64 ({logdet, quad, loglik} per problem, as
+ * tlr_solve_logdet; loglik = -inf for a problem whose status is not OK).
+ * Work queued on `stream` before the call is finished before any problem
+ * starts; `stream` waits for every problem's work.  The call returns once
+ * every problem has been issued (each evaluation synchronises its own
+ * stream per tile column, as tlr_potrf does).  Results are bitwise those of
+ * tlr_loglik on each problem alone.  Batched calls on one device are
+ * serialised by the library. */
+tlr_status tlr_loglik_batched(tlr_batch_plan bplan, const double *const *h_locs, const double *const *h_z,
+                              const tlr_theta *h_theta, double tol, void *d_ws, size_t ws_bytes, double *d_out,
+                              int32_t workers, void *stream);
 
 /* Synchronises `stream`, then reads the device status word. */
 /* Per-tile ranks held in the workspace: which = 0 gives those of Sigma's

@@ -67,6 +67,10 @@ _SIGNATURES = {
     "tlr_potrf": (I32, [P, P, SZ, P]),
     "tlr_solve_logdet": (I32, [P, P, P, SZ, P, P]),
     "tlr_loglik": (I32, [P, P, P, _Theta, F64, P, SZ, P, P, P]),
+    "tlr_batch_plan_create": (I32, [ctypes.POINTER(P), I32, P, P, I32, I32, U32]),
+    "tlr_batch_plan_destroy": (None, [P]),
+    "tlr_batch_ws_bytes": (SZ, [P]),
+    "tlr_loglik_batched": (I32, [P, P, P, P, F64, P, SZ, P, I32, P]),
     "tlr_status_read": (I32, [P, P, ctypes.POINTER(DevInfo), P]),
     "tlr_strerror": (ctypes.c_char_p, [I32]),
     "tlr_version": (ctypes.c_char_p, []),
@@ -240,6 +244,54 @@ class Plan:
         _check(lib().tlr_status_read(self._h, _ptr(ws), ctypes.byref(info), _stream()), "tlr_status_read")
         return {"code": info.code, "name": status_name(info.code), "tile": (info.tile_i, info.tile_j),
                 "max_rank": info.max_rank, "rank_sum": info.rank_sum}
+
+
+class BatchPlan:
+    """Owns a tlr_batch_plan: one plan per problem, one workspace for all."""
+
+    def __init__(self, ns, nbs, maxrank: int = 0, precision: str = "fp64", dense_tiles: bool = False):
+        L = lib()
+        count = len(ns)
+        n_arr = (ctypes.c_int64 * count)(*[int(v) for v in ns])
+        nb_arr = (ctypes.c_int32 * count)(*[int(v) for v in nbs])
+        h = ctypes.c_void_p()
+        _check(L.tlr_batch_plan_create(ctypes.byref(h), count, ctypes.cast(n_arr, P), ctypes.cast(nb_arr, P),
+                                       maxrank, PRECISIONS[precision], 1 if dense_tiles else 0),
+               "tlr_batch_plan_create")
+        self._h = h
+        self.count = count
+        self.ns = list(ns)
+        self.ws_bytes = L.tlr_batch_ws_bytes(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tlr_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def loglik(self, ws, locs, zs, thetas, tol, workers: int = 8, out=None):
+        """locs, zs: lists of device tensors (one per problem); returns count x 3."""
+        count = self.count
+        if len(locs) != count or len(zs) != count or len(thetas) != count:
+            raise ValueError("one location set, observation vector and theta per problem")
+        for t in list(locs) + list(zs):
+            _ptr(t)
+        lp = (ctypes.c_void_p * count)(*[t.data_ptr() for t in locs])
+        zp = (ctypes.c_void_p * count)(*[t.data_ptr() for t in zs])
+        th = (_Theta * count)(*[_Theta(*map(float, t)) for t in thetas])
+        out = torch.empty(count, 3, dtype=torch.float64, device=ws.device) if out is None else out
+        _check(lib().tlr_loglik_batched(self._h, ctypes.cast(lp, P), ctypes.cast(zp, P), ctypes.cast(th, P),
+                                        float(tol), _ptr(ws), ws.numel(), _ptr(out), int(workers), _stream()),
+               "tlr_loglik_batched")
+        return out
 
 
 def diag_gemm(a, b, c, alpha=1.0, beta=0.0, trans_a=False, trans_b=False):

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libtlrmle.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["order.hip", "gensolve.hip", "gemm.hip", "small.hip", "cholqr.hip", "peak.hip", "ktimer.cpp", "tlr.cpp",
-           "api.cpp"]
+           "batch.cpp", "api.cpp"]
 
 # -packed-fp32-ops off: hand-written float code must not be lowered to packed
 # FP32 instructions on this target.

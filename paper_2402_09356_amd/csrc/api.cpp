@@ -14,6 +14,13 @@ tlr_status status_read(tlr_plan p, const void *d_ws, tlr_devinfo *out, hipStream
 void plan_shape(tlr_plan p, int64_t *n, int32_t *nb, int32_t *nt, int32_t *maxrank);
 tlr_status tile_read(tlr_plan p, const void *d_ws, int i, int j, double *d_out, int32_t *h_rank, hipStream_t s);
 tlr_status ranks_read(tlr_plan p, const void *d_ws, int which, int32_t *d_out, hipStream_t s);
+tlr_status batch_plan_create(tlr_batch_plan *out, int count, const int64_t *n, const int32_t *nb, int maxrank,
+                             tlr_precision prec, uint32_t flags);
+void batch_plan_destroy(tlr_batch_plan bp);
+size_t batch_ws_bytes(tlr_batch_plan bp);
+tlr_status loglik_batched(tlr_batch_plan bp, const double *const *locs, const double *const *z,
+                          const tlr_theta *theta, double tol, void *d_ws, size_t ws_bytes, double *d_out,
+                          int workers, hipStream_t s);
 }  // namespace tlr
 
 static inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
@@ -68,6 +75,21 @@ tlr_status tlr_potrf(tlr_plan plan, void *d_ws, size_t ws_bytes, void *stream) {
 tlr_status tlr_solve_logdet(tlr_plan plan, const double *d_z, void *d_ws, size_t ws_bytes, double *d_out,
                             void *stream) {
     return tlr::solve_logdet(plan, d_z, d_ws, ws_bytes, d_out, as_stream(stream));
+}
+
+tlr_status tlr_batch_plan_create(tlr_batch_plan *out, int32_t count, const int64_t *h_n, const int32_t *h_nb,
+                                 int32_t maxrank, tlr_precision precision, uint32_t flags) {
+    return tlr::batch_plan_create(out, count, h_n, h_nb, maxrank, precision, flags);
+}
+
+void tlr_batch_plan_destroy(tlr_batch_plan bplan) { tlr::batch_plan_destroy(bplan); }
+
+size_t tlr_batch_ws_bytes(tlr_batch_plan bplan) { return tlr::batch_ws_bytes(bplan); }
+
+tlr_status tlr_loglik_batched(tlr_batch_plan bplan, const double *const *h_locs, const double *const *h_z,
+                              const tlr_theta *h_theta, double tol, void *d_ws, size_t ws_bytes, double *d_out,
+                              int32_t workers, void *stream) {
+    return tlr::loglik_batched(bplan, h_locs, h_z, h_theta, tol, d_ws, ws_bytes, d_out, workers, as_stream(stream));
 }
 
 tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tlr_theta theta, double tol,

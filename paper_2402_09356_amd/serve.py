@@ -9,7 +9,7 @@ admitted as soon as a worker and memory free up, so evaluations of different
 problems overlap on the device (continuous batching).  Every evaluation is
 deterministic, so a result is bitwise the same alone and in the mix.
 
-    python -m paper_2402_09356_amd.serve --bench     # the serving workload
+    python -m paper_2402_09356_amd.serve --bench     # the serving workload, FP64 and mixed
 """
 from __future__ import annotations
 
@@ -196,63 +196,193 @@ def run_fits(server: Server, fits, think_mean_s: float, seed: int, max_evals: in
     return results
 
 
+class _Stop(Exception):
+    pass
+
+
+def run_open_loop(server: Server, fits, rate: float | None, total: int, seed: int, max_evals: int = 100000,
+                  progress=None):
+    """Nelder-Mead fits as clients, gated by an open-loop arrival process.
+
+    An arrival thread releases one ticket at each time of a Poisson process
+    of the given rate (seeded); a fit that has its next proposal ready takes a
+    ticket and submits that proposal as a request, so requests enter the
+    server at the arrival times whatever the server's backlog (open loop),
+    while each request still carries its fit's own next simplex point.  With
+    rate None every fit submits as soon as its previous result is back
+    (saturation, which measures capacity).  Stops once `total` requests have
+    completed; returns the completed requests in completion order."""
+    from .mle import nelder_mead
+
+    import synthetic
+
+    tickets = threading.Semaphore(0)
+    stop = threading.Event()
+    done = []
+    lock = threading.Lock()
+
+    def objective_for(pid, nu):
+        def objective(x):
+            if stop.is_set():
+                raise _Stop()
+            if rate is not None:
+                while not tickets.acquire(timeout=0.05):
+                    if stop.is_set():
+                        raise _Stop()
+            th = (math.exp(x[0]), math.exp(x[1]), nu)
+            req = server.submit(pid, th)
+            val = req.future.result()
+            with lock:
+                done.append(req)
+                if progress is not None and len(done) % 100 == 0:
+                    progress(len(done))
+                if len(done) >= total:
+                    stop.set()
+            return -val
+        return objective
+
+    def client(pid, start, nu):
+        while not stop.is_set():
+            try:
+                nelder_mead(objective_for(pid, nu), np.log(start[:2]), step=0.1, ftol=1e-9, max_evals=max_evals)
+            except _Stop:
+                return
+            # a fit that converged starts again from its starting point
+
+    def arrivals():
+        gaps = synthetic.poisson_arrivals(4 * total + 100, rate, seed)
+        t0 = time.perf_counter()
+        for t in gaps:
+            while not stop.is_set():
+                dt = t - (time.perf_counter() - t0)
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.05))
+            if stop.is_set():
+                return
+            tickets.release()
+
+    threads = [threading.Thread(target=client, args=f) for f in fits]
+    if rate is not None:
+        threads.append(threading.Thread(target=arrivals))
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    return done
+
+
 def latency_stats(reqs):
     lat = np.array([r.finished - r.submitted for r in reqs]) * 1e3
     return {"count": int(lat.size), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean())}
 
 
-def _bench(args):
+def workload_problems(precision: str, tol: float, mix=(19, 10, 3), maxrank: int = 0, device="cuda:0"):
+    """The serving workload: fits over three resident datasets (jittered grids,
+    nu = 1/2, Hilbert order, Z ~ N(0, Sigma(1, 0.1, 1/2)) from the stored draws
+    of the blocked dense oracle): n = 10,000 (nb = 400), 40,000 (nb = 800) and
+    90,000 (nb = 900).  One resident problem per dataset; fit f of the mix
+    starts from (0.5, 0.05) * exp(0.1 N(0, I)) (seeded), nu fixed at 1/2."""
+    import os
+
     import torch
 
     import synthetic
     from . import binding as B
 
-    dev = torch.device("cuda:0")
-    sizes = {10_000: (100, 400), 40_000: (200, 800), 90_000: (300, 900)}
-    mix = [10_000] * args.n10 + [40_000] * args.n40 + [90_000] * args.n90
+    root = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden")
+    datasets = [("c5-10k", 5, 0, 400), ("c2-1", 2, 1, 800), ("c3", 3, 0, 900)]
+    dev = torch.device(device)
     problems, fits = [], []
-    for pid, n in enumerate(mix):
-        m, nb = sizes[n]
-        locs = synthetic.jittered_grid(m, synthetic.seed_for(5, synthetic.SEED_LOCS, pid))
-        z = synthetic.standard_normal(n, synthetic.seed_for(5, synthetic.SEED_Z, pid))
+    for pid, (name, cfg, extra, nb) in enumerate(datasets):
+        with open(os.path.join(root, f"large_{name}.json")) as fh:
+            rec = json.load(fh)
+        z = np.load(os.path.join(root, rec["z_file"]))
+        locs = synthetic.jittered_grid(rec["m"], synthetic.seed_for(cfg, synthetic.SEED_LOCS, extra))
         dl = torch.from_numpy(locs).to(dev)
         perm = B.reorder(dl, "hilbert")
         ol, oz = B.apply_perm(perm, dl, torch.from_numpy(z).to(dev))
-        plan = B.Plan(n, nb, maxrank=args.maxrank)
-        problems.append(Problem(pid, plan, ol, oz, args.tol))
-        fits.append((pid, (0.5, 0.05, 0.5), 0.5))
+        plan = B.Plan(rec["n"], nb, maxrank=maxrank, precision=precision)
+        problems.append(Problem(pid, plan, ol, oz, tol))
+    starts = synthetic.theta_perturbations((0.5, 0.05), sum(mix), synthetic.seed_for(5, synthetic.SEED_THETA), 0.1)
+    f = 0
+    for pid, count in enumerate(mix):
+        for _ in range(count):
+            fits.append((pid, tuple(float(v) for v in starts[f]), 0.5))
+            f += 1
+    return problems, fits
+
+
+def _serve_once(precision, args):
+    import torch
+
+    problems, fits = workload_problems(precision, args.tol)
+    out = {"precision": precision}
+    log = lambda k: print(f"# {precision}: {k} completed", file=sys.stderr, flush=True)  # noqa: E731
+    # capacity: every fit submits back to back
     srv = Server(problems, workers=args.workers, hbm_budget_bytes=int(args.hbm_gib * 2**30))
+    run_open_loop(srv, fits, None, args.warmup, seed=1, progress=log)  # warm
     t0 = time.perf_counter()
-    run_fits(srv, fits, args.think_ms * 1e-3, seed=5000, max_evals=args.evals_per_fit)
-    wall = time.perf_counter() - t0
+    sat = run_open_loop(srv, fits, None, args.capacity_evals, seed=1, progress=log)
+    cap = len(sat) / (time.perf_counter() - t0)
     srv.close()
-    done = [r for r in srv.completed if r.future.exception() is None]
-    out = {"metric": "served l(theta) evals/s", "value": len(done) / wall, "unit": "evals/s", "wall_s": wall,
-           "latency": latency_stats(done), "workers": args.workers, "fits": len(fits),
-           "mix": {"10k": args.n10, "40k": args.n40, "90k": args.n90}, "tol": args.tol, "precision": "fp64",
-           "workspace_gib": srv.pool.allocated / 2**30}
+    out["capacity_evals_per_s"] = cap
+    rate = args.load * cap
+    # open loop at `load` x capacity: warm-up, then the measured completions
+    srv = Server(problems, workers=args.workers, hbm_budget_bytes=int(args.hbm_gib * 2**30))
+    t_start = time.perf_counter()
+    done = run_open_loop(srv, fits, rate, args.warmup + args.completions,
+                         seed=synthetic_seed(args.seed), progress=log)
+    srv.close()
+    done.sort(key=lambda r: r.finished)
+    measured = done[args.warmup:]
+    # throughput over the measured window: from the last warm-up completion
+    # to the last completion
+    t_meas0 = done[args.warmup - 1].finished
+    t_meas1 = measured[-1].finished
+    ok = [r for r in measured if r.future.exception() is None and np.isfinite(r.future.result())]
+    out.update({"arrival_rate_per_s": rate, "load": args.load, "completions": len(measured),
+                "finite": len(ok), "evals_per_s": len(ok) / (t_meas1 - t_meas0),
+                "wall_s": time.perf_counter() - t_start, "latency": latency_stats(measured),
+                "workspace_gib": srv.pool.allocated / 2**30})
     by_n = {}
-    for r in done:
+    for r in measured:
         by_n.setdefault(srv.problems[r.pid].plan.n, []).append(r)
     out["latency_by_n"] = {str(k): latency_stats(v) for k, v in sorted(by_n.items())}
-    print(json.dumps(out))
+    del problems
+    torch.cuda.empty_cache()
+    return out
+
+
+def synthetic_seed(base: int) -> int:
+    import synthetic
+
+    return synthetic.seed_for(5, synthetic.SEED_ARRIVALS, base)
+
+
+def _bench(args):
+    res = {"metric": "served l(theta) evals/s", "unit": "evals/s", "workers": args.workers,
+           "fits": {"10k": 19, "40k": 10, "90k": 3}, "tol": args.tol,
+           "arrivals": f"open-loop Poisson at {args.load} x measured capacity, seeded"}
+    for prec in ("fp64", "mixed_fp32"):
+        res[prec] = _serve_once(prec, args)
+        print(f"# {prec}: {json.dumps(res[prec])}", file=sys.stderr, flush=True)
+    res["value"] = res["mixed_fp32"]["evals_per_s"]
+    print(json.dumps(res))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--bench", action="store_true")
-    ap.add_argument("--n10", type=int, default=19)
-    ap.add_argument("--n40", type=int, default=10)
-    ap.add_argument("--n90", type=int, default=3)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--hbm-gib", type=float, default=200.0)
-    ap.add_argument("--maxrank", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-7)
-    # each fit waits this long between a result and its next proposal; with 32
-    # fits this offers about two thirds of the saturated capacity
-    ap.add_argument("--think-ms", type=float, default=3500.0)
-    ap.add_argument("--evals-per-fit", type=int, default=12)
+    ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of measured capacity")
+    ap.add_argument("--capacity-evals", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--completions", type=int, default=1000)
+    ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     if args.bench:
         _bench(args)

@@ -8,6 +8,8 @@ Workloads (jittered m x m grid on the unit square, sigma2 = 1):
 * ``c1``: m = 40 (n = 1,600), nu = 1/2, beta = 0.1 -- the small smoke case;
 * ``c3``: m = 300 (n = 90,000), nu = 1/2, beta = 0.1 -- the n = 90,000 point of
   the paper's Section 5.3.1 timing study;
+* ``c5-10k``: m = 100 (n = 10,000), nu = 1/2, beta = 0.1 -- the 10k problems of
+  the serving workload;
 * ``c2-<cell>``: m = 200 (n = 40,000), one (nu, beta) cell of the grid
   nu in {1/2, 3/2} x beta in {0.03, 0.1, 0.3} (cell = 3 * i_nu + i_beta).
 
@@ -47,6 +49,8 @@ def workload(name: str):
         return dict(config=1, extra=0, m=40, theta=(1.0, 0.1, 0.5))
     if name == "c3":
         return dict(config=3, extra=0, m=300, theta=(1.0, 0.1, 0.5))
+    if name == "c5-10k":
+        return dict(config=5, extra=0, m=100, theta=(1.0, 0.1, 0.5))
     if name.startswith("c2-"):
         cell = int(name[3:])
         nu, beta = C2_CELLS[cell]
