@@ -257,6 +257,10 @@ tlr_status tlr_loglik_batched(tlr_batch_plan bplan, const double *const *h_locs,
                               const tlr_theta *h_theta, double tol, void *d_ws, size_t ws_bytes, double *d_out,
                               int32_t workers, void *stream);
 
+/* tlr_status_read for problem `index` of a batch (synchronises `stream`). */
+tlr_status tlr_batch_status_read(tlr_batch_plan bplan, const void *d_ws, int32_t index, tlr_devinfo *out,
+                                 void *stream);
+
 /* Synchronises `stream`, then reads the device status word. */
 /* Per-tile ranks held in the workspace: which = 0 gives those of Sigma's
  * compressed tiles (after tlr_compress), which = 1 those of the factor L

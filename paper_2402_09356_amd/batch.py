@@ -141,10 +141,15 @@ def _bench(args):
         seq = batch.sequential()[:, 2]
         t_seq = time.perf_counter() - t0
         finite = int(np.sum(np.isfinite(bat)))
+        codes = {}
+        for p in range(len(bat)):
+            if not np.isfinite(bat[p]):
+                name = batch.plan.status(batch.ws, p)["name"]
+                codes[name] = codes.get(name, 0) + 1
         same = bool(all((a == b) or (np.isnan(a) and np.isnan(b)) for a, b in zip(seq, bat)))
         # only finite results count as completed evaluations
         rec[prec] = {"evals_per_s": finite / t_bat, "finite_results": finite,
-                     "nonfinite_results": len(bat) - finite,
+                     "nonfinite_results": len(bat) - finite, "nonfinite_status": codes,
                      "sequential_evals_per_s": int(np.sum(np.isfinite(seq))) / t_seq, "speedup": t_seq / t_bat,
                      "bitwise_equal_to_sequential": same, "nb": sorted(set(batch.nbs)),
                      "sum_n": int(sum(batch.ns))}

@@ -70,6 +70,7 @@ _SIGNATURES = {
     "tlr_batch_plan_create": (I32, [ctypes.POINTER(P), I32, P, P, I32, I32, U32]),
     "tlr_batch_plan_destroy": (None, [P]),
     "tlr_batch_ws_bytes": (SZ, [P]),
+    "tlr_batch_status_read": (I32, [P, P, I32, ctypes.POINTER(DevInfo), P]),
     "tlr_loglik_batched": (I32, [P, P, P, P, F64, P, SZ, P, I32, P]),
     "tlr_status_read": (I32, [P, P, ctypes.POINTER(DevInfo), P]),
     "tlr_strerror": (ctypes.c_char_p, [I32]),
@@ -292,6 +293,13 @@ class BatchPlan:
                                         float(tol), _ptr(ws), ws.numel(), _ptr(out), int(workers), _stream()),
                "tlr_loglik_batched")
         return out
+
+    def status(self, ws, index: int) -> dict:
+        info = DevInfo()
+        _check(lib().tlr_batch_status_read(self._h, _ptr(ws), int(index), ctypes.byref(info), _stream()),
+               "tlr_batch_status_read")
+        return {"code": info.code, "name": status_name(info.code), "tile": (info.tile_i, info.tile_j),
+                "max_rank": info.max_rank, "rank_sum": info.rank_sum}
 
 
 def diag_gemm(a, b, c, alpha=1.0, beta=0.0, trans_a=False, trans_b=False):

@@ -17,6 +17,7 @@ tlr_status ranks_read(tlr_plan p, const void *d_ws, int which, int32_t *d_out, h
 tlr_status batch_plan_create(tlr_batch_plan *out, int count, const int64_t *n, const int32_t *nb, int maxrank,
                              tlr_precision prec, uint32_t flags);
 void batch_plan_destroy(tlr_batch_plan bp);
+tlr_status batch_status_read(tlr_batch_plan bp, const void *d_ws, int index, tlr_devinfo *out, hipStream_t s);
 size_t batch_ws_bytes(tlr_batch_plan bp);
 tlr_status loglik_batched(tlr_batch_plan bp, const double *const *locs, const double *const *z,
                           const tlr_theta *theta, double tol, void *d_ws, size_t ws_bytes, double *d_out,
@@ -85,6 +86,11 @@ tlr_status tlr_batch_plan_create(tlr_batch_plan *out, int32_t count, const int64
 void tlr_batch_plan_destroy(tlr_batch_plan bplan) { tlr::batch_plan_destroy(bplan); }
 
 size_t tlr_batch_ws_bytes(tlr_batch_plan bplan) { return tlr::batch_ws_bytes(bplan); }
+
+tlr_status tlr_batch_status_read(tlr_batch_plan bplan, const void *d_ws, int32_t index, tlr_devinfo *out,
+                                 void *stream) {
+    return tlr::batch_status_read(bplan, d_ws, index, out, as_stream(stream));
+}
 
 tlr_status tlr_loglik_batched(tlr_batch_plan bplan, const double *const *h_locs, const double *const *h_z,
                               const tlr_theta *h_theta, double tol, void *d_ws, size_t ws_bytes, double *d_out,

@@ -28,6 +28,7 @@ tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws,
 tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks, hipStream_t s);
 tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s);
 tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_bytes, double *d_out, hipStream_t s);
+tlr_status status_read(tlr_plan p, const void *d_ws, tlr_devinfo *out, hipStream_t s);
 }  // namespace tlr
 
 struct tlr_batch_plan_s {
@@ -174,6 +175,11 @@ tlr_status loglik_batched(tlr_batch_plan bp, const double *const *locs, const do
     }
     (void)hipEventDestroy(ready);
     return st;
+}
+
+tlr_status batch_status_read(tlr_batch_plan bp, const void *d_ws, int index, tlr_devinfo *out, hipStream_t s) {
+    if (!bp || !d_ws || !out || index < 0 || index >= (int)bp->plans.size()) return TLR_E_INVAL;
+    return status_read(bp->plans[index], static_cast<const char *>(d_ws) + bp->offset[index], out, s);
 }
 
 }  // namespace tlr

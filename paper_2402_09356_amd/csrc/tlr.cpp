@@ -524,8 +524,11 @@ tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega,
 // orthonormality to rounding level.  Optionally R = R4 R3 R2 R1 (panel = Q R).
 // With passes = 2 or 3 the result spans the panel's range with every
 // direction above the rounding level lifted to unit size, which is all the
-// first basis of the range finder needs.
-tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int passes = 4) {
+// first basis of the range finder needs.  With `shifted` = 1 and passes = 3
+// (one shifted pass, two deflating ones) the directions above about 1e-11 of
+// the panel's norm come out orthonormal and the rest are deflated: enough when
+// the truncation threshold lies above that (see full_passes).
+tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int passes = 4, int shifted = 2) {
     const int nb = c.p->nb;
     const size_t nj = jobs.size();
     int kmx = 0;
@@ -560,7 +563,7 @@ tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int pa
     TLR_PUSH(dsd, c, sd);
     StagedGemm sa, sb, sc;
     std::vector<GemmDesc> a, b, d2;
-    if (want_r) {
+    if (want_r && passes == 4) {
         // Rt = R4 R3 R2 R1, accumulated through T
         for (auto &jb : jobs) {
             a.push_back(gd(jb.Rp[3], jb.k, jb.Rp[2], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
@@ -570,19 +573,30 @@ tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int pa
         TLR_TRY(stage_gemms(c, false, false, a, &sa));
         TLR_TRY(stage_gemms(c, false, false, b, &sb));
         TLR_TRY(stage_gemms(c, false, false, d2, &sc));
+    } else if (want_r && passes == 3) {
+        // Rt = R3 R2 R1 through T
+        for (auto &jb : jobs) {
+            a.push_back(gd(jb.Rp[2], jb.k, jb.Rp[1], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+            b.push_back(gd(jb.T, jb.k, jb.Rp[0], jb.k, jb.Rt, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+        }
+        TLR_TRY(stage_gemms(c, false, false, a, &sa));
+        TLR_TRY(stage_gemms(c, false, false, b, &sb));
+    } else if (want_r) {
+        return TLR_E_UNSUPPORTED;
     }
     for (int it = 0; it < passes; ++it) {
         const SmallDesc *dp = dsd + (size_t)it * nj;
         const SmallDesc *hp = sd.data() + (size_t)it * nj;
         TLR_TRY(launch_staged(c, sg));
-        TLR_LAUNCH(c, chol_small(dp, (int)nj, kmx, it < 2 ? 1 : 2, c.params(), c.s, hp));
+        TLR_LAUNCH(c, chol_small(dp, (int)nj, kmx, it < shifted ? 1 : 2, c.params(), c.s, hp));
         TLR_LAUNCH(c, trsm_rows(dp, (int)nj, nb, kmx, c.s, hp));
     }
     if (want_r) {
         TLR_TRY(launch_staged(c, sa));
         TLR_TRY(launch_staged(c, sb));
         TLR_TRY(launch_staged(c, sc));
-        for (auto &jb : jobs) std::swap(jb.Rt, jb.T);
+        if (passes == 4)
+            for (auto &jb : jobs) std::swap(jb.Rt, jb.T);
     }
     return TLR_OK;
 }
@@ -603,8 +617,20 @@ int q1_passes(const tlr_plan_s *p, double sigma2, double tol) {
     return tol >= 1e-12 * (double)p->nb * sigma2 ? 2 : 3;
 }
 
+// Passes for the second and third bases (Q2, and Qw with Rt): one shifted
+// and two deflating passes resolve every direction above about 1e-11 of the
+// panel's norm, which is enough under the float32 rounding floor of a mixed
+// plan (about 1e-7 of the tile's norm); a float64 plan takes two shifted and
+// two deflating passes (with three, a smooth field's l at n = 40,000 moved by
+// 3e-8 n at tol = 1e-7, above its bound).
+int full_passes(const tlr_plan_s *p, double sigma2, double tol) {
+    (void)sigma2;
+    (void)tol;
+    return p->mixed ? 3 : 4;
+}
+
 tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int Rj, bool exact_svd,
-                int passes_q1) {
+                int passes_q1, int passes_full) {
     if (jobs.empty()) return TLR_OK;
     // widest sample first: its work-groups, the longest, are dispatched
     // first in every batched launch below (the order of the results is not
@@ -616,9 +642,9 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int 
     TLR_TRY(apply_op(c, jobs, false, true, false, Yj, Rj));   // Yb = T W
     TLR_TRY(cholqr(c, jobs, false, false, passes_q1));       // Yb = Q1 (only its span is used)
     TLR_TRY(apply_op(c, jobs, true, false, true, Yj, Rj));    // Zb = T^T Q1
-    TLR_TRY(cholqr(c, jobs, true, false));                   // Zb = Q2
+    TLR_TRY(cholqr(c, jobs, true, false, passes_full, passes_full == 3 ? 1 : 2));   // Zb = Q2
     TLR_TRY(apply_op(c, jobs, false, false, false, Yj, Rj));  // Yb = T Q2
-    TLR_TRY(cholqr(c, jobs, false, true));                   // Yb = Qw, Rt
+    TLR_TRY(cholqr(c, jobs, false, true, passes_full, passes_full == 3 ? 1 : 2));   // Yb = Qw, Rt
     if (!exact_svd) {
         std::vector<SmallDesc> sq;
         for (auto &jb : jobs) {
@@ -934,7 +960,8 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
             }
             TLR_PUSH(dg, c, gens);
             TLR_LAUNCH(c, gen_tiles_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), mc, s));
-            TLR_TRY(rsvd(c, jobs, tol, nullptr, 0, p->svd_trunc, q1_passes(p, hb.dp.sigma2, tol)));
+            TLR_TRY(rsvd(c, jobs, tol, nullptr, 0, p->svd_trunc, q1_passes(p, hb.dp.sigma2, tol),
+                         full_passes(p, hb.dp.sigma2, tol)));
             Ctx::StatRead sr;
             TLR_TRY(c.read_stats(jobs, sr));
             TLR_TRY(c.sync_reset());
@@ -1205,7 +1232,8 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         TLR_LAUNCH(c, schur_noise(dnz, (int)nz.size(), nt, c.nrm_s(), c.nrm_l(), s));
                     }
                     if (!jobs.empty())
-                        TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, p->svd_trunc, q1_passes(p, hb.dp.sigma2, tol)));
+                        TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, p->svd_trunc, q1_passes(p, hb.dp.sigma2, tol),
+                                     full_passes(p, hb.dp.sigma2, tol)));
                     TLR_TRY(issue_diag());
                     Ctx::StatRead sr;
                     TLR_TRY(c.read_stats(jobs, sr));
