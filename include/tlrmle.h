@@ -45,7 +45,8 @@ enum {
     TLR_E_HIP = 4,          /* a HIP runtime call failed */
     TLR_NOT_SPD = 16,       /* device: non-positive pivot in a diagonal tile */
     TLR_RANK_OVERFLOW = 17, /* device: a tile rank exceeded the plan's rank cap */
-    TLR_E_DOMAIN = 18       /* device: a location outside [0,1]^2 or not finite */
+    TLR_E_DOMAIN = 18,      /* device: a location outside [0,1]^2 or not finite */
+    TLR_ARENA_OVERFLOW = 19 /* the factors outgrew the workspace's rank budget */
 };
 
 /* Orderings of paper Section 3: NONE = generation order ("No Order"),
@@ -173,11 +174,20 @@ tlr_status tlr_plan_create(tlr_plan *out, int64_t n, int32_t nb, int32_t maxrank
                            tlr_precision precision, uint32_t flags);
 void tlr_plan_destroy(tlr_plan plan);
 
-/* Bytes of device workspace one evaluation needs (diagonal tiles, low-rank
- * factor slots of 2*nb*maxrank words per off-diagonal tile, sketch buffers,
- * status word).  The caller allocates it; the library never allocates device
- * memory on the evaluation path. */
-size_t tlr_plan_ws_bytes(tlr_plan plan);
+/* Bytes of device workspace one evaluation needs: a fixed part (diagonal
+ * tiles, sketch and small-matrix buffers, descriptors, tables, status word)
+ * and a factor arena that holds the low-rank factors U, V of every
+ * off-diagonal tile in slots of 2 * nb * w entries (w >= the tile's rank;
+ * 8-byte entries, 4-byte in a TLR_MIXED_FP32 plan).
+ * rank_budget: the total of the slot widths w the arena must hold (the sum of
+ * the off-diagonal ranks, plus the growth of tiles whose rank rises in the
+ * factorisation); <= 0 means maxrank for every tile, which always suffices.
+ * A smaller budget sizes admission by the ranks a problem really has; if the
+ * factors outgrow it, the evaluation stops with TLR_ARENA_OVERFLOW (l = -inf).
+ * Every call takes the caller's workspace size and uses all of it: a larger
+ * buffer is a larger arena.  The library never allocates device memory on the
+ * evaluation path. */
+size_t tlr_plan_ws_bytes(tlr_plan plan, int64_t rank_budget);
 
 /* Tile geometry of the plan (any pointer may be NULL). */
 void tlr_plan_shape(tlr_plan plan, int64_t *n, int32_t *nb, int32_t *nt, int32_t *maxrank);

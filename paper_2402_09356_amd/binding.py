@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libtlrmle.so")
 ORDERINGS = {"none": 0, "random": 1, "morton": 2, "hilbert": 3, "kdtree": 4}
 PRECISIONS = {"fp64": 0, "mixed_fp32": 1}
 STATUS = {0: "TLR_OK", 1: "TLR_E_INVAL", 2: "TLR_E_NOMEM", 3: "TLR_E_UNSUPPORTED", 4: "TLR_E_HIP",
-          16: "TLR_NOT_SPD", 17: "TLR_RANK_OVERFLOW", 18: "TLR_E_DOMAIN"}
+          16: "TLR_NOT_SPD", 17: "TLR_RANK_OVERFLOW", 18: "TLR_E_DOMAIN", 19: "TLR_ARENA_OVERFLOW"}
 
 
 class TlrError(RuntimeError):
@@ -59,7 +59,7 @@ _SIGNATURES = {
     "tlr_apply_perm": (I32, [P, I64, P, P, P, P, I32, P]),
     "tlr_plan_create": (I32, [ctypes.POINTER(P), I64, I32, I32, I32, U32]),
     "tlr_plan_destroy": (None, [P]),
-    "tlr_plan_ws_bytes": (SZ, [P]),
+    "tlr_plan_ws_bytes": (SZ, [P, I64]),
     "tlr_plan_shape": (None, [P, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32),
                               ctypes.POINTER(I32)]),
     "tlr_gen_tiles": (I32, [P, P, _Theta, P, SZ, P]),
@@ -168,9 +168,10 @@ class Plan:
     """Owns a tlr_plan handle; workspaces are torch uint8 device tensors."""
 
     def __init__(self, n: int, nb: int, maxrank: int = 0, precision: str = "fp64", dense_tiles: bool = False,
-                 truncation: str = "qrcp"):
+                 truncation: str = "qrcp", rank_budget: int = 0):
         """dense_tiles: keep over-rank off-diagonal tiles dense (TLR_PLAN_DENSE_TILES);
-        truncation: "qrcp" (pivoted QR, default) or "svd" (TLR_PLAN_SVD_TRUNCATION)."""
+        truncation: "qrcp" (pivoted QR, default) or "svd" (TLR_PLAN_SVD_TRUNCATION);
+        rank_budget: total factor-slot width of the workspace (0: maxrank per tile)."""
         L = lib()
         h = ctypes.c_void_p()
         flags = (1 if dense_tiles else 0) | (2 if truncation == "svd" else 0)
@@ -187,7 +188,8 @@ class Plan:
         L.tlr_plan_shape(h, ctypes.byref(n_), ctypes.byref(nb_), ctypes.byref(nt_), ctypes.byref(mr_))
         self.nt = nt_.value
         self.maxrank = mr_.value
-        self.ws_bytes = L.tlr_plan_ws_bytes(h)
+        self.rank_budget = int(rank_budget)
+        self.ws_bytes = L.tlr_plan_ws_bytes(h, self.rank_budget)
 
     def close(self):
         if getattr(self, "_h", None):

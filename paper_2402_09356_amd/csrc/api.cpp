@@ -6,6 +6,7 @@ namespace tlr {
 tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precision prec, uint32_t flags);
 void plan_destroy(tlr_plan p);
 size_t plan_ws_bytes(tlr_plan p);
+size_t plan_ws_bytes_budget(tlr_plan p, int64_t rank_budget);
 tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws, size_t ws_bytes, hipStream_t s);
 tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks, hipStream_t s);
 tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s);
@@ -54,7 +55,7 @@ tlr_status tlr_plan_create(tlr_plan *out, int64_t n, int32_t nb, int32_t maxrank
 
 void tlr_plan_destroy(tlr_plan plan) { tlr::plan_destroy(plan); }
 
-size_t tlr_plan_ws_bytes(tlr_plan plan) { return tlr::plan_ws_bytes(plan); }
+size_t tlr_plan_ws_bytes(tlr_plan plan, int64_t rank_budget) { return tlr::plan_ws_bytes_budget(plan, rank_budget); }
 
 void tlr_plan_shape(tlr_plan plan, int64_t *n, int32_t *nb, int32_t *nt, int32_t *maxrank) {
     tlr::plan_shape(plan, n, nb, nt, maxrank);
@@ -125,6 +126,7 @@ const char *tlr_strerror(tlr_status code) {
         case TLR_NOT_SPD: return "matrix not positive definite";
         case TLR_RANK_OVERFLOW: return "tile rank above the rank cap";
         case TLR_E_DOMAIN: return "location outside the unit square";
+        case TLR_ARENA_OVERFLOW: return "factor arena full (rank budget too small)";
         default: return "unknown status";
     }
 }

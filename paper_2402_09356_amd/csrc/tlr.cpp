@@ -8,12 +8,17 @@
 //   diag      nt dense nb x nb diagonal tiles (column-major)
 //   rsig, rL  nt x nt int32 rank tables: compressed Sigma, current factor
 //   tstat     per off-diagonal tile: {rank used, numerical rank, retry flag, -}
-//   slots     per off-diagonal tile (i > j, index i(i-1)/2 + j): U then V,
-//             each nb x maxrank column-major
+//   tofs      per off-diagonal tile (i > j, index i(i-1)/2 + j): offset and
+//             width of its factor slot in the factor arena, then the arena's
+//             fill mark
 //   yvec      padded solve vector
 //   omega     nb x kmax standard-normal test matrix of the range finder
 //   desc      kernel descriptor staging area
 //   arena     per-wave scratch (dense tiles, sketches, small matrices)
+//   fac       factor arena, to the end of the caller's workspace: each tile's
+//             U then V (nb x w, column-major, w >= its rank), placed by the
+//             host as ranks become known (first fit at the fill mark; a
+//             recompressed tile reuses its slot when the new rank fits)
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -31,8 +36,8 @@ struct tlr_plan_s {
     int nb, nt, rcap, kmax, pover, min_tail, k0;
     tlr_precision prec;
     uint32_t flags;
-    size_t off_params, off_x, off_y, off_diag, off_rsig, off_rL, off_tstat, off_slots, off_yvec, off_omega,
-        off_desc, off_arena, off_knu, off_dense, off_wide, off_nrm_s, off_nrm_l, off_noise;
+    size_t off_params, off_x, off_y, off_diag, off_rsig, off_rL, off_tstat, off_tofs, off_yvec, off_omega,
+        off_desc, off_arena, off_knu, off_dense, off_wide, off_nrm_s, off_nrm_l, off_noise, off_fac;
     bool mixed;  // TLR_MIXED_FP32: low-rank factors stored in float32
     int fw;      // bytes per stored factor entry (8, or 4 when mixed)
     bool dense_ok;   // TLR_PLAN_DENSE_TILES: over-rank tiles kept dense in the wide slots
@@ -228,13 +233,69 @@ struct Ctx {
     double *wideV(int i, int j) const { return wideU(i, j) + (int64_t)p->nb * p->nb; }
     // low-rank factors of tile (i, j): float64, or float32 in a mixed plan
     // (fac_types() gives the GEMM type bits of such an operand)
+    // factor slots: host copy of the tile table (loaded by load_slots)
+    struct Slot {
+        int64_t off;  // first entry of U in the factor arena
+        int32_t w;    // columns reserved for U and for V
+        int32_t pad;
+    };
+    std::vector<Slot> slots;
+    int64_t fac_fill = 0;    // entries of the arena in use
+    size_t ws_size = 0;      // the caller's workspace bytes (bounds the arena)
     void *U(int i, int j) const {
         if (dense(i, j)) return wideU(i, j);
-        return ws + p->off_slots + (tile_index(i, j) * 2 * (int64_t)p->nb * p->rcap) * p->fw;
+        const Slot &sl = slots[(size_t)tile_index(i, j)];
+        return ws + p->off_fac + sl.off * p->fw;
     }
     void *V(int i, int j) const {
         if (dense(i, j)) return wideV(i, j);
-        return ws + p->off_slots + (tile_index(i, j) * 2 * (int64_t)p->nb * p->rcap + (int64_t)p->nb * p->rcap) * p->fw;
+        const Slot &sl = slots[(size_t)tile_index(i, j)];
+        return ws + p->off_fac + (sl.off + (int64_t)p->nb * sl.w) * p->fw;
+    }
+    int64_t fac_capacity() const { return (int64_t)((ws_size - p->off_fac) / p->fw); }
+    // A slot of width w for tile (i, j): the tile's own when it is wide
+    // enough, else a new one at the fill mark.  False when the arena is full.
+    bool take_slot(int i, int j, int w) {
+        Slot &sl = slots[(size_t)tile_index(i, j)];
+        if (w <= sl.w) return true;
+        const int64_t need = 2 * (int64_t)p->nb * w;
+        if (fac_fill + need > fac_capacity()) return false;
+        sl.off = fac_fill;
+        sl.w = w;
+        fac_fill += need;
+        return true;
+    }
+    void reset_slots() {
+        slots.assign((size_t)std::max<int64_t>(p->ntiles, 1), Slot{0, 0, 0});
+        fac_fill = 0;
+    }
+    tlr_status load_slots() {
+        slots.resize((size_t)std::max<int64_t>(p->ntiles, 1) + 1);
+        TLR_HIP(hipMemcpyAsync(slots.data(), ws + p->off_tofs, sizeof(Slot) * slots.size(), hipMemcpyDeviceToHost,
+                               s));
+        TLR_HIP(hipStreamSynchronize(s));
+        fac_fill = slots.back().off;
+        slots.pop_back();
+        return TLR_OK;
+    }
+    tlr_status store_slots() {
+        slots.push_back(Slot{fac_fill, 0, 0});
+        TLR_HIP(hipMemcpyAsync(ws + p->off_tofs, slots.data(), sizeof(Slot) * slots.size(), hipMemcpyHostToDevice,
+                               s));
+        TLR_HIP(hipStreamSynchronize(s));  // the host table is edited again after this
+        slots.pop_back();
+        return TLR_OK;
+    }
+    // first failure wins: record a failure the host detected
+    tlr_status host_fail(int code, int i, int j) {
+        int32_t cur = 0;
+        TLR_HIP(hipMemcpyAsync(&cur, &params()->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        TLR_HIP(hipStreamSynchronize(s));
+        if (cur != 0) return TLR_OK;
+        const int32_t v[3] = {code, i, j};
+        TLR_HIP(hipMemcpyAsync(&params()->status, v, 3 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        TLR_HIP(hipStreamSynchronize(s));
+        return TLR_OK;
     }
     int fa() const { return p->mixed ? kGemmA32 : 0; }   // factor as left operand
     int fb() const { return p->mixed ? kGemmB32 : 0; }   // factor as right operand
@@ -451,6 +512,7 @@ size_t job_words(int nb, int k, int r, int R, bool dense) {
     w += (size_t)k;                   // S
     w += (size_t)std::max(r, 1) * k;  // H
     w += (size_t)std::max(R, 1) * k;  // F
+    w += 2 * (size_t)nb * k;          // U, V results (width k >= rank) before they go to their slot
     return w + 16 * 64;               // alignment slack
 }
 
@@ -818,7 +880,7 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->off_rsig = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
     p->off_rL = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
     p->off_tstat = take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(p->ntiles, 1));
-    p->off_slots = take((size_t)p->fw * 2 * (size_t)nb * rcap * (size_t)p->ntiles);
+    p->off_tofs = take(sizeof(int64_t) * 2 * ((size_t)std::max<int64_t>(p->ntiles, 1) + 1));
     p->off_nrm_s = take(sizeof(double) * (size_t)p->nt * p->nt);
     p->off_nrm_l = take(sizeof(double) * (size_t)p->nt * p->nt);
     p->off_noise = take(sizeof(double) * (size_t)std::max<int64_t>(p->ntiles, 1));
@@ -852,7 +914,10 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     arena = std::min<size_t>(arena, (size_t)16 << 30);
     p->arena_bytes = arena;
     p->off_arena = take(arena);
-    p->ws_bytes = off;
+    // the factor arena runs to the end of the caller's workspace; the default
+    // size holds a slot of maxrank columns for every tile
+    p->off_fac = off;
+    p->ws_bytes = off + align_up((size_t)p->fw * 2 * (size_t)nb * rcap * (size_t)p->ntiles, 256);
     *out = p;
     return TLR_OK;
 }
@@ -861,11 +926,17 @@ void plan_destroy(tlr_plan p) { delete p; }
 
 size_t plan_ws_bytes(tlr_plan p) { return p ? p->ws_bytes : 0; }
 
+size_t plan_ws_bytes_budget(tlr_plan p, int64_t rank_budget) {
+    if (!p) return 0;
+    if (rank_budget <= 0) return p->ws_bytes;
+    return p->off_fac + align_up((size_t)p->fw * 2 * (size_t)p->nb * (size_t)rank_budget, 256);
+}
+
 // ------------------------------------------------------------ generation --
 
 tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws, size_t ws_bytes, hipStream_t s) {
     if (!p || !d_locs || !d_ws) return TLR_E_INVAL;
-    if (ws_bytes < p->ws_bytes) return TLR_E_NOMEM;
+    if (ws_bytes < p->off_fac) return TLR_E_NOMEM;
     MaternConst mc{};
     if (!make_matern_const(th.sigma2, th.beta, th.nu, &mc)) return TLR_E_INVAL;
     Ctx c(p, d_ws, s);
@@ -902,8 +973,10 @@ tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws,
 tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks, hipStream_t s) {
     if (!p || !d_ws) return TLR_E_INVAL;
     if (!(tol >= 0.0) || !std::isfinite(tol)) return TLR_E_INVAL;
-    if (ws_bytes < p->ws_bytes) return TLR_E_NOMEM;
+    if (ws_bytes < p->off_fac) return TLR_E_NOMEM;
     Ctx c(p, d_ws, s);
+    c.ws_size = ws_bytes;
+    c.reset_slots();
     const int nt = p->nt, nb = p->nb;
     ParamsBlock hb{};
     TLR_HIP(hipMemcpyAsync(&hb, c.pblock(), sizeof(ParamsBlock), hipMemcpyDeviceToHost, s));
@@ -924,6 +997,7 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
         int i, j, k;
     };
     std::vector<Pending> pending;
+    bool arena_full = false;  // a factor did not fit the arena: stop (status set)
     for (int i = 1; i < nt; ++i)
         for (int j = 0; j < i; ++j) {
             const int kfull = std::min(tile_rows(p, i), tile_rows(p, j));
@@ -931,10 +1005,10 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
             const int want = (h >= 0) ? h + p->pover : p->k0;
             pending.push_back({i, j, clamp_k(p, want, kfull)});
         }
-    while (!pending.empty()) {
+    while (!pending.empty() && !arena_full) {
         std::vector<Pending> retry;
         size_t pos = 0;
-        while (pos < pending.size()) {
+        while (pos < pending.size() && !arena_full) {
             c.arena_used = 0;
             std::vector<Job> jobs;
             std::vector<GenDesc> gens;
@@ -950,8 +1024,10 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
                 double *A = c.alloc((size_t)nb * nb);
                 if (!A || !alloc_job(c, jb, 0)) return TLR_E_NOMEM;
                 jb.A = A;
-                jb.Uout = c.U(pt.i, pt.j);
-                jb.Vout = c.V(pt.i, pt.j);
+                // results go to their slot once the rank is known
+                jb.Uout = c.alloc_fac((size_t)nb * pt.k);
+                jb.Vout = c.alloc_fac((size_t)nb * pt.k);
+                if (!jb.Uout || !jb.Vout) return TLR_E_NOMEM;
                 jb.stat = c.tstat(tile_index(pt.i, pt.j));
                 gens.push_back(GenDesc{A, pt.i * nb, pt.j * nb, nb, 0});
                 jobs.push_back(jb);
@@ -978,6 +1054,8 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
             }
             std::vector<std::pair<int, int>> dz;
             std::vector<const double *> dsrc;
+            std::vector<CopyDesc> put;
+            int64_t put_max = 0;
             for (size_t q = 0; q < jobs.size(); ++q) {
                 const Job &jb = jobs[q];
                 if (st[4 * q + 2]) {
@@ -992,16 +1070,30 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
                             dsrc.push_back(jb.A);
                             rk = nb;
                         }
+                    } else if (rk > 0) {
+                        if (!c.take_slot(jb.i, jb.j, rk)) {
+                            if (!arena_full) TLR_TRY(c.host_fail(TLR_ARENA_OVERFLOW, jb.i, jb.j));
+                            arena_full = true;
+                        } else {
+                            put.push_back(CopyDesc{jb.Uout, c.U(jb.i, jb.j), (int64_t)nb * rk, p->mixed ? 2 : 0});
+                            put.push_back(CopyDesc{jb.Vout, c.V(jb.i, jb.j), (int64_t)nb * rk, p->mixed ? 2 : 0});
+                            put_max = std::max<int64_t>(put_max, (int64_t)nb * rk);
+                        }
                     }
                     ranks[(size_t)jb.i * nt + jb.j] = rk;
                 }
+            }
+            // into their slots before the next wave reuses the job buffers
+            if (!put.empty()) {
+                TLR_PUSH(dput, c, put);
+                TLR_LAUNCH(c, copy_batched(dput, (int)put.size(), put_max, s));
             }
             // before the next wave reuses the arena that holds the tiles
             TLR_TRY(make_dense(c, dz, dsrc));
         }
         pending.swap(retry);
     }
-    if (p->mixed && p->ntiles > 0) {
+    if (p->mixed && p->ntiles > 0 && !arena_full) {
         // ||V_ij||_F = ||U_ij V_ij^T||_F (U has orthonormal columns): the
         // scale of each stored tile's float32 rounding
         std::vector<NormDesc> nd;
@@ -1013,6 +1105,7 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
         TLR_LAUNCH(c, factor_norms(dnd, (int)nd.size(), nb, s));
     }
     TLR_TRY(c.store_dense());
+    TLR_TRY(c.store_slots());
     TLR_HIP(hipMemcpyAsync(c.rsig(), ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
     TLR_HIP(hipMemcpyAsync(c.rL(), ranks.data(), sizeof(int32_t) * ranks.size(), hipMemcpyHostToDevice, s));
     std::vector<int32_t> out_ranks = ranks;
@@ -1031,7 +1124,7 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
 
 tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
     if (!p || !d_ws) return TLR_E_INVAL;
-    if (ws_bytes < p->ws_bytes) return TLR_E_NOMEM;
+    if (ws_bytes < p->off_fac) return TLR_E_NOMEM;
     Ctx c(p, d_ws, s);
     const int nt = p->nt, nb = p->nb;
     ParamsBlock hb{};
@@ -1041,7 +1134,9 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
     TLR_HIP(hipStreamSynchronize(s));
     const double tol = hb.tol;
     if (hb.dp.status != 0) return TLR_OK;  // already failed: l = -inf
+    c.ws_size = ws_bytes;
     TLR_TRY(c.load_dense());
+    TLR_TRY(c.load_slots());
     for (int i = 0; i < nt; ++i)
         for (int j = 0; j < i; ++j)
             if (r[(size_t)i * nt + j] < 0) return TLR_OK;  // overflow recorded by compress
@@ -1144,8 +1239,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         if (dz)
                             words += (size_t)nb * nb + 64;
                         else
-                            words += job_words(nb, kk[i], rij, Rj, false) +
-                                     (p->dense_ok ? 2 * (size_t)nb * p->rcap + (size_t)nb * nb + 256 : 0);
+                            words += job_words(nb, kk[i], rij, Rj, false) + (p->dense_ok ? (size_t)nb * nb + 256 : 0);
                         if (c.arena_used + words * sizeof(double) > p->arena_bytes && !(jobs.empty() && djobs.empty()))
                             break;
                         Job jb{};
@@ -1165,16 +1259,15 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                             if (!jb.D) return TLR_E_NOMEM;
                         } else {
                             if (!alloc_job(c, jb, Rj)) return TLR_E_NOMEM;
+                            // results land in temporaries and go to the tile's slot once
+                            // the rank is known; the old factors stay intact meanwhile
+                            // (a retry, or the dense form, still reads them)
+                            jb.Uout = c.alloc_fac((size_t)nb * jb.k);
+                            jb.Vout = c.alloc_fac((size_t)nb * jb.k);
+                            if (!jb.Uout || !jb.Vout) return TLR_E_NOMEM;
                             if (p->dense_ok) {
-                                // results land in temporaries: the old factors stay intact
-                                // in case the tile turns out to need the dense form
-                                jb.Uout = c.alloc((size_t)nb * p->rcap);
-                                jb.Vout = c.alloc((size_t)nb * p->rcap);
                                 jb.D = c.alloc((size_t)nb * nb);
-                                if (!jb.Uout || !jb.Vout || !jb.D) return TLR_E_NOMEM;
-                            } else {
-                                jb.Uout = c.U(i, j);
-                                jb.Vout = c.V(i, j);
+                                if (!jb.D) return TLR_E_NOMEM;
                             }
                         }
                         // X_i blocks: U_ik (V_ik^T V_jk)
@@ -1269,9 +1362,13 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         } else {
                             const int rk = st[4 * q];
                             r[(size_t)jb.i * nt + j] = rk;
-                            if (p->dense_ok && rk > 0) {
-                                keep.push_back(CopyDesc{jb.Uout, c.U(jb.i, j), (int64_t)nb * rk, 0});
-                                keep.push_back(CopyDesc{jb.Vout, c.V(jb.i, j), (int64_t)nb * rk, 0});
+                            if (rk > 0 && !c.take_slot(jb.i, j, rk)) {
+                                if (!failed) TLR_TRY(c.host_fail(TLR_ARENA_OVERFLOW, jb.i, j));
+                                failed = true;
+                            } else if (rk > 0) {
+                                const int cv = p->mixed ? 2 : 0;
+                                keep.push_back(CopyDesc{jb.Uout, c.U(jb.i, j), (int64_t)nb * rk, cv});
+                                keep.push_back(CopyDesc{jb.Vout, c.V(jb.i, j), (int64_t)nb * rk, cv});
                                 keep_max = std::max<int64_t>(keep_max, (int64_t)nb * rk);
                             }
                         }
@@ -1290,7 +1387,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         }
                         TLR_TRY(make_dense(c, dt, ds));
                     }
-                    if (!keep.empty() || !conv.empty()) TLR_TRY(c.sync_reset());
+                    if (!conv.empty() || (p->dense_ok && !keep.empty())) TLR_TRY(c.sync_reset());
                 }
                 todo.swap(retry);
             }
@@ -1339,6 +1436,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
     }
     TLR_TRY(c.sync_reset());
     TLR_TRY(c.store_dense());
+    TLR_TRY(c.store_slots());
     TLR_HIP(hipMemcpyAsync(c.rL(), r.data(), sizeof(int32_t) * r.size(), hipMemcpyHostToDevice, s));
     TLR_HIP(hipStreamSynchronize(s));
     return TLR_OK;
@@ -1348,10 +1446,12 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
 
 tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_bytes, double *d_out, hipStream_t s) {
     if (!p || !d_z || !d_ws || !d_out) return TLR_E_INVAL;
-    if (ws_bytes < p->ws_bytes) return TLR_E_NOMEM;
+    if (ws_bytes < p->off_fac) return TLR_E_NOMEM;
     Ctx c(p, d_ws, s);
     const int nt = p->nt, nb = p->nb;
+    c.ws_size = ws_bytes;
     TLR_TRY(c.load_dense());
+    TLR_TRY(c.load_slots());
     TLR_TRY(pad_copy(d_z, p->n, p->npad, c.yvec(), s));
     const size_t gb = gemv_desc_bytes();
     std::vector<char> hv(gb * std::max<int64_t>(p->ntiles, 1));
@@ -1436,6 +1536,7 @@ tlr_status tile_read(tlr_plan p, const void *d_ws, int i, int j, double *d_out, 
     Ctx c(p, const_cast<void *>(d_ws), s);
     const int nb = p->nb;
     TLR_TRY(c.load_dense());
+    TLR_TRY(c.load_slots());
     if (i == j) {
         TLR_HIP(hipMemcpyAsync(d_out, c.diag(i), sizeof(double) * nb * nb, hipMemcpyDeviceToDevice, s));
         TLR_HIP(hipStreamSynchronize(s));

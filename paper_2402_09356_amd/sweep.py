@@ -1,86 +1,119 @@
-"""Rank and storage sweep over orderings (the medium-scale configuration).
+"""Rank, storage and accuracy sweep over orderings (the medium-scale study).
 
-For each cell (nu, beta, ordering, nb, tol) on an m x m jittered grid: the
-per-tile ranks after compression, their histogram, the off-diagonal storage
-in MB (2 nb r 8 bytes per low-rank tile, nb^2 8 per dense one: the quantity of the
-paper's Table "memory"), l(theta_true) and the time of one evaluation.  Ranks do not depend
-on the observations, so Z is white noise here.
+The workload is a 200 x 200 jittered grid (n = 40,000) per (nu, beta) with
+nu in {1/2, 3/2} and beta in {0.03, 0.1, 0.3}, sigma2 = 1, observations
+Z ~ N(0, Sigma(theta_true)) from the blocked dense oracle's stored draw of
+that dataset.  For each cell (dataset, ordering, nb, tol) one evaluation of
+l(theta_true) gives, from that same evaluation: l, its distance to the
+oracle's stored l, the per-tile ranks of Sigma's compressed tiles and their
+histogram, the off-diagonal storage in MB (2 nb r words per low-rank tile,
+nb^2 per dense one, 8-byte words: the quantity of the paper's Table
+"memory"), and the time of a second, warm evaluation.  Optionally a
+Nelder-Mead fit of all three parameters from (0.5, 0.05, 1.0) per dataset.
 
-    python -m paper_2402_09356_amd.sweep --m 200 --nu 0.5 --beta 0.03 0.1 0.3 \\
-        --orderings random morton hilbert kdtree --nb 800 --tol 1e-7
+    python -m paper_2402_09356_amd.sweep --fits > sweep.jsonl
 """
 from __future__ import annotations
 
 import argparse
 import json
+import os
 import time
 
 import numpy as np
 
 BINS = (0, 1, 11, 26, 51, 101, 201, 10**9)
+CELLS = [(nu, beta) for nu in (0.5, 1.5) for beta in (0.03, 0.1, 0.3)]
+GOLDEN = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden")
 
 
-def run_cell(m, nu, beta, kind, nb, tol, exact_ranks=False, seed_cfg=2, cell=0, dense_tiles=False):
+def dataset(cell: int, kind: str, device):
+    """Ordered locations and observations of one (nu, beta) dataset, and its
+    stored oracle values."""
     import torch
 
     import synthetic
     from . import binding as B
 
-    dev = torch.device("cuda:0")
-    n = m * m
-    locs = synthetic.jittered_grid(m, synthetic.seed_for(seed_cfg, synthetic.SEED_LOCS, cell))
-    z = synthetic.standard_normal(n, synthetic.seed_for(seed_cfg, synthetic.SEED_Z, cell))
-    dl = torch.from_numpy(locs).to(dev)
-    perm = B.reorder(dl, kind, synthetic.seed_for(seed_cfg, synthetic.SEED_ORDER, cell))
-    ol, oz = B.apply_perm(perm, dl, torch.from_numpy(z).to(dev))
-    plan = B.Plan(n, nb, maxrank=nb // 2, dense_tiles=dense_tiles, truncation="svd" if exact_ranks else "qrcp")
-    ws = plan.workspace(dev)
+    with open(os.path.join(GOLDEN, f"large_c2-{cell}.json")) as fh:
+        rec = json.load(fh)
+    z = np.load(os.path.join(GOLDEN, rec["z_file"]))
+    locs = synthetic.jittered_grid(rec["m"], synthetic.seed_for(2, synthetic.SEED_LOCS, cell))
+    dl = torch.from_numpy(locs).to(device)
+    perm = B.reorder(dl, kind, synthetic.seed_for(2, synthetic.SEED_ORDER, cell))
+    ol, oz = B.apply_perm(perm, dl, torch.from_numpy(z).to(device))
+    return ol, oz, rec
+
+
+def run_cell(cell, kind, nb, tol, device="cuda:0"):
+    import torch
+
+    from . import binding as B
+
+    nu, beta = CELLS[cell]
+    ol, oz, rec = dataset(cell, kind, torch.device(device))
+    n = rec["n"]
     theta = (1.0, beta, nu)
-    out = plan.loglik(ws, ol, oz, theta, tol)  # warm
+    # over-rank tiles are kept dense, as the paper's storage table counts them
+    plan = B.Plan(n, nb, maxrank=nb // 2, dense_tiles=True)
+    ws = plan.workspace(device)
+    out = plan.loglik(ws, ol, oz, theta, tol).cpu().numpy()
+    st = plan.status(ws)
+    r = plan.ranks(ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = plan.loglik(ws, ol, oz, theta, tol)
+    plan.loglik(ws, ol, oz, theta, tol)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    st = plan.status(ws)
     nt = plan.nt
-    # ranks, l and the time all come from the same (timed) evaluation
-    r = plan.ranks(ws)
     rk = np.asarray([int(r[i, j]) for i in range(nt) for j in range(i)])
-    over = int(np.sum(rk == -1))
     dense = int(np.sum(rk == -2))
     low = rk[rk >= 0]
     hist = np.histogram(low, bins=np.asarray(BINS))[0].tolist()
-    storage_mb = float(2 * nb * low.sum() * 8 / 1e6 + (over + dense) * nb * nb * 8 / 1e6)
-    return {"n": n, "nu": nu, "beta": beta, "ordering": kind, "nb": nb, "tol": tol,
-            "loglik": float(out[2].item()), "eval_s": dt, "status": st["code"],
+    storage_mb = float(2 * nb * low.sum() * 8 / 1e6 + dense * nb * nb * 8 / 1e6)
+    ref = rec["values"][0]["loglik"]
+    dl_abs = abs(float(out[2]) - ref)
+    return {"n": n, "nu": nu, "beta": beta, "ordering": kind, "nb": nb, "tol": tol, "status": st["name"],
+            "loglik": float(out[2]), "loglik_oracle": ref, "abs_dl": dl_abs, "abs_dl_per_n": dl_abs / n,
+            "within_bound": bool(dl_abs <= n * max(1e-8, 0.1 * tol)), "eval_s": dt,
             "rank_mean": float(low.mean()) if low.size else None, "rank_max": int(low.max()) if low.size else None,
-            "hist_bins": list(BINS), "hist": hist, "overflow_tiles": over, "dense_tiles": dense,
-            "offdiag_storage_MB": storage_mb,
-            "rank_mode": "singular values" if exact_ranks else "pivoted QR"}
+            "hist_bins": list(BINS), "hist": hist, "dense_tiles": dense, "offdiag_storage_MB": storage_mb}
+
+
+def fit_cell(cell, nb=800, tol=1e-7, kind="hilbert", device="cuda:0", max_evals=400, ftol=1e-6):
+    """theta-hat of a Nelder-Mead fit of (sigma2, beta, nu) from (0.5, 0.05, 1.0)."""
+    import torch
+
+    from . import binding as B
+    from . import mle
+
+    nu, beta = CELLS[cell]
+    ol, oz, rec = dataset(cell, kind, torch.device(device))
+    plan = B.Plan(rec["n"], nb, maxrank=nb // 2, dense_tiles=True)
+    ws = plan.workspace(device)
+    t0 = time.perf_counter()
+    res = mle.fit(plan, ws, ol, oz, tol, start=(0.5, 0.05, 1.0), ftol=ftol, max_evals=max_evals)
+    wall = time.perf_counter() - t0
+    return {"fit": True, "n": rec["n"], "theta_true": [1.0, beta, nu], "ordering": kind, "nb": nb, "tol": tol,
+            "theta_hat": list(res.theta), "loglik_hat": res.loglik, "evals": res.evals, "converged": res.converged,
+            "f_hat": res.f_identifiable, "f_true": 1.0 * beta ** (-2.0 * nu), "wall_s": wall, "ftol": ftol}
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--m", type=int, default=200)
-    ap.add_argument("--nu", type=float, nargs="+", default=[0.5])
-    ap.add_argument("--beta", type=float, nargs="+", default=[0.03, 0.1, 0.3])
+    ap.add_argument("--cells", type=int, nargs="+", default=list(range(len(CELLS))))
     ap.add_argument("--orderings", nargs="+", default=["random", "morton", "hilbert", "kdtree"])
-    ap.add_argument("--nb", type=int, nargs="+", default=[800])
-    ap.add_argument("--tol", type=float, nargs="+", default=[1e-7])
-    ap.add_argument("--exact-ranks", action="store_true")
-    ap.add_argument("--dense-tiles", action="store_true", help="keep over-rank tiles dense")
+    ap.add_argument("--nb", type=int, nargs="+", default=[400, 800])
+    ap.add_argument("--tol", type=float, nargs="+", default=[1e-7, 1e-9])
+    ap.add_argument("--fits", action="store_true", help="also fit theta per dataset (Hilbert, nb 800, tol 1e-7)")
     args = ap.parse_args()
-    cell = 0
-    for nu in args.nu:
-        for beta in args.beta:
-            cell += 1
-            for kind in args.orderings:
-                for nb in args.nb:
-                    for tol in args.tol:
-                        rec = run_cell(args.m, nu, beta, kind, nb, tol, args.exact_ranks, cell=cell,
-                                       dense_tiles=args.dense_tiles)
-                        print(json.dumps(rec), flush=True)
+    for cell in args.cells:
+        for kind in args.orderings:
+            for nb in args.nb:
+                for tol in args.tol:
+                    print(json.dumps(run_cell(cell, kind, nb, tol)), flush=True)
+        if args.fits:
+            print(json.dumps(fit_cell(cell)), flush=True)
 
 
 if __name__ == "__main__":

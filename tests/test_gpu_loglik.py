@@ -336,3 +336,62 @@ def test_dense_tiles_random_order():
     assert plan.status(ws)["code"] == 0
     assert abs(out[2] - dense) <= bound(900, tol, comp.loglik - dense)
     assert (plan.ranks(ws)[np.tril_indices(plan.nt, -1)] == -2).sum() >= 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_evaluation_allocates_no_device_memory(precision):
+    """The workspace is the only device memory an evaluation uses: once the
+    library's streams and staging pools exist (first evaluation), further
+    evaluations leave the device's free memory unchanged."""
+    import gc
+
+    dev = device()
+    theta, nb, tol = (1.0, 0.1, 0.5), 900, 1e-7
+    locs = synthetic.jittered_grid(90, synthetic.seed_for(3, synthetic.SEED_LOCS, 7))
+    z = synthetic.standard_normal(8100, 5)
+    plan = B.Plan(8100, nb, precision=precision)
+    ws = plan.workspace()
+    dl, dz = to_dev(locs), to_dev(z)
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    plan.loglik(ws, dl, dz, theta, tol, out=out)
+    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    try:
+        free_before = torch.cuda.mem_get_info(dev)[0]
+        for th in [(1.2, 0.08, 0.5), (0.9, 0.12, 0.7)]:
+            plan.loglik(ws, dl, dz, th, tol, out=out)
+        torch.cuda.synchronize()
+        free_after = torch.cuda.mem_get_info(dev)[0]
+    finally:
+        gc.enable()
+    assert free_after == free_before
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_rank_budget_sizes_the_factor_arena(precision):
+    """A workspace sized by the ranks a problem has (the sum of Sigma's and
+    L's off-diagonal ranks) gives bitwise the result of the default
+    (maxrank per tile); a budget below Sigma's rank sum stops with
+    TLR_ARENA_OVERFLOW and l = -inf."""
+    device()
+    theta, nb, tol = (1.0, 0.1, 0.5), 200, 1e-9
+    locs, z = make_problem(40, theta, "hilbert")
+    dl, dz = to_dev(locs), to_dev(z)
+    full = B.Plan(1600, nb, precision=precision)
+    ws = full.workspace()
+    ref = full.loglik(ws, dl, dz, theta, tol).cpu().numpy()
+    low = np.tril_indices(full.nt, -1)
+    rs, rl = full.ranks(ws)[low], full.ranks(ws, factor=True)[low]
+    budget = int(rs[rs > 0].sum() + rl[rl > 0].sum())
+    tight = B.Plan(1600, nb, precision=precision, rank_budget=budget)
+    assert tight.ws_bytes < full.ws_bytes
+    ws2 = tight.workspace()
+    got = tight.loglik(ws2, dl, dz, theta, tol).cpu().numpy()
+    print(f"{precision}: rank budget {budget}, workspace {tight.ws_bytes} vs {full.ws_bytes} bytes", flush=True)
+    assert got.tobytes() == ref.tobytes()
+    short = B.Plan(1600, nb, precision=precision, rank_budget=int(rs[rs > 0].sum()) // 2)
+    ws3 = short.workspace()
+    bad = short.loglik(ws3, dl, dz, theta, tol).cpu().numpy()
+    assert bad[2] == -np.inf
+    assert short.status(ws3)["code"] == 19
