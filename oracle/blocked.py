@@ -80,19 +80,49 @@ class _Store:
             os.remove(path)
 
 
-class BlockedCholesky:
-    """Lower Cholesky factor of Sigma(theta) held as b x b blocks."""
+def _truncate_tiles(block: np.ndarray, r0: int, c0: int, nb: int, tol: float, maxrank: int) -> None:
+    """Replace every strictly-lower nb x nb tile (P > Q, global tile indices)
+    inside a block whose first row / column are r0 / c0 by its SVD truncated
+    at tol (singular values > tol kept; a tile above maxrank stays exact) --
+    the tile-truncated covariance of ``tlr.compressed_matrix``, block by block."""
+    rows, cols = block.shape
+    for pr in range(r0 // nb, (r0 + rows + nb - 1) // nb):
+        for qc in range(c0 // nb, (c0 + cols + nb - 1) // nb):
+            if pr <= qc:
+                continue
+            a0, a1 = max(pr * nb, r0) - r0, min((pr + 1) * nb, r0 + rows) - r0
+            b0, b1 = max(qc * nb, c0) - c0, min((qc + 1) * nb, c0 + cols) - c0
+            u, sv, vt = np.linalg.svd(block[a0:a1, b0:b1], full_matrices=False)
+            r = int(np.count_nonzero(sv > tol))
+            if r <= maxrank:
+                block[a0:a1, b0:b1] = (u[:, :r] * sv[:r]) @ vt[:r, :]
 
-    def __init__(self, locs: np.ndarray, theta, b: int = 4096, path: str | None = None, log=None):
+
+class BlockedCholesky:
+    """Lower Cholesky factor of Sigma(theta) held as b x b blocks.
+
+    With ``tiles = (nb, tol, maxrank)`` the factor is that of the
+    tile-truncated covariance instead (paper Section 2: every off-diagonal
+    nb x nb tile replaced by its truncated SVD), for the error that
+    compression alone causes; b must then be a multiple of nb."""
+
+    def __init__(self, locs: np.ndarray, theta, b: int = 4096, path: str | None = None, log=None, tiles=None):
         locs = np.asarray(locs, dtype=np.float64)
         self.n = locs.shape[0]
         self.store = _Store(self.n, b, path)
         bd = self.store.bounds
         nblk = self.store.nblk
+        if tiles is not None and b % tiles[0] != 0:
+            raise ValueError("the block size must be a multiple of the tile size")
         # Sigma's blocks on and below the diagonal
         for i in range(nblk):
             for j in range(i + 1):
-                self.store.put(i, j, matern.covariance(locs[bd[i][0]:bd[i][1]], locs[bd[j][0]:bd[j][1]], theta))
+                blk = matern.covariance(locs[bd[i][0]:bd[i][1]], locs[bd[j][0]:bd[j][1]], theta)
+                if tiles is not None:
+                    _truncate_tiles(blk, bd[i][0], bd[j][0], *tiles)
+                self.store.put(i, j, blk)
+            if log is not None and tiles is not None:
+                log(f"block row {i + 1}/{nblk} assembled")
         # right-looking blocked factorisation
         for k in range(nblk):
             try:
@@ -157,9 +187,11 @@ class BlockedCholesky:
         self.store.close()
 
 
-def loglik_blocked(locs, z, theta, b: int = 4096, path: str | None = None, log=None) -> likelihood.LogLik:
-    """l(theta) by the blocked factorisation (raises NotPositiveDefinite)."""
-    f = BlockedCholesky(locs, theta, b, path, log)
+def loglik_blocked(locs, z, theta, b: int = 4096, path: str | None = None, log=None,
+                   tiles=None) -> likelihood.LogLik:
+    """l(theta) by the blocked factorisation (raises NotPositiveDefinite);
+    tiles = (nb, tol, maxrank) gives l of the tile-truncated covariance."""
+    f = BlockedCholesky(locs, theta, b, path, log, tiles)
     try:
         return f.loglik(z)
     finally:

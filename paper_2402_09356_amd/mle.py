@@ -104,12 +104,13 @@ class FitResult:
     f_identifiable: float  # sigma2 * beta^(-2 nu)
 
 
-def fit(plan, ws, locs, z, tol, start=(0.5, 0.05, 1.0), nu=None, ftol=1e-9, max_evals=1000, step=0.1):
+def fit(plan, ws, locs, z, tol, start=(0.5, 0.05, 1.0), nu=None, ftol=1e-9, max_evals=1000, step=0.1,
+        progress=None):
     """MLE of theta = (sigma2, beta, nu) by l(theta) evaluations on the GPU.
 
     plan/ws: a binding.Plan and its workspace; locs/z: ordered device tensors.
     With `nu` given the smoothness is held fixed and only (sigma2, beta) are
-    fitted."""
+    fitted.  `progress(evals, best_l)` is called every 25 evaluations."""
     import torch
 
     out = torch.empty(3, dtype=torch.float64, device=z.device)
@@ -119,10 +120,18 @@ def fit(plan, ws, locs, z, tol, start=(0.5, 0.05, 1.0), nu=None, ftol=1e-9, max_
             return (math.exp(x[0]), math.exp(x[1]), math.exp(x[2]))
         return (math.exp(x[0]), math.exp(x[1]), float(nu))
 
+    count = [0]
+    best = [-math.inf]
+
     def objective(x):
         th = theta_of(x)
         plan.loglik(ws, locs, z, th, tol, out=out)
-        return -float(out[2].item())
+        val = float(out[2].item())
+        count[0] += 1
+        best[0] = max(best[0], val)
+        if progress is not None and count[0] % 25 == 0:
+            progress(count[0], best[0])
+        return -val
 
     x0 = np.log(np.asarray(start if nu is None else start[:2], dtype=np.float64))
     res = nelder_mead(objective, x0, step=step, ftol=ftol, max_evals=max_evals)

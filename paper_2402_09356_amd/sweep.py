@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import sys
 import time
 
 import numpy as np
@@ -92,7 +93,9 @@ def fit_cell(cell, nb=800, tol=1e-7, kind="hilbert", device="cuda:0", max_evals=
     plan = B.Plan(rec["n"], nb, maxrank=nb // 2, dense_tiles=True)
     ws = plan.workspace(device)
     t0 = time.perf_counter()
-    res = mle.fit(plan, ws, ol, oz, tol, start=(0.5, 0.05, 1.0), ftol=ftol, max_evals=max_evals)
+    log = lambda k, b: print(f"# fit cell {cell}: {k} evaluations, best l {b:.6f}", file=sys.stderr,  # noqa: E731
+                             flush=True)
+    res = mle.fit(plan, ws, ol, oz, tol, start=(0.5, 0.05, 1.0), ftol=ftol, max_evals=max_evals, progress=log)
     wall = time.perf_counter() - t0
     return {"fit": True, "n": rec["n"], "theta_true": [1.0, beta, nu], "ordering": kind, "nb": nb, "tol": tol,
             "theta_hat": list(res.theta), "loglik_hat": res.loglik, "evals": res.evals, "converged": res.converged,

@@ -71,3 +71,19 @@ def test_blocked_not_positive_definite():
     locs = np.array([[0.2, 0.2], [0.2, 0.2], [0.5, 0.6], [0.1, 0.9]])  # duplicated location
     with pytest.raises(OL.NotPositiveDefinite):
         OB.loglik_blocked(locs, np.ones(4), (1.0, 0.1, 1.5), b=2)
+
+
+@pytest.mark.parametrize("nb,tol", [(100, 1e-5), (150, 1e-7)])
+def test_tile_truncated_blocked_equals_compressed_matrix(nb, tol):
+    # the tile-truncated covariance assembled block by block gives the same l
+    # as the whole-matrix construction of the tile oracle
+    from oracle import tlr as OT
+
+    locs = synthetic.jittered_grid(24, 51)  # n = 576
+    z = synthetic.standard_normal(576, 52)
+    theta = (1.0, 0.15, 1.5)
+    ref, _ = OT.compressed_loglik(locs, z, theta, nb, tol, maxrank=nb)
+    got = OB.loglik_blocked(locs, z, theta, b=3 * nb, tiles=(nb, tol, nb))
+    assert got.loglik == pytest.approx(ref.loglik, rel=1e-10, abs=1e-8)
+    exact = OL.loglik_dense(locs, z, theta).loglik
+    assert abs(got.loglik - exact) > 0  # truncation did change the matrix
