@@ -342,7 +342,7 @@ def main():
     st = plan.status(ws)
     lat_ms = np.asarray(lat) * 1e3
     workload = (f"{args.config}: n={n} jittered grid, nu=0.5 beta=0.1 sigma2=1, {kind} order, nb={nb}, "
-                f"tol={tol:g}, theta=theta_true*exp(0.2 N(0,I)) per step")
+                f"tol={tol:g}, theta=theta_true*exp(0.2 N(0,I)) per step, {args.precision}")
     rec = {
         "metric": "l(theta) evals/s, n=90k TLR Matern",
         "value": args.steps / total,

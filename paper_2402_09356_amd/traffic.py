@@ -9,6 +9,9 @@ scales every kernel's figure.
 
     python -m paper_2402_09356_amd.traffic --fetch DIR --write DIR \\
         --copy-mib 1024 --workload "..." --out profiles/traffic.json
+
+With --mfma DIR instead, it summarises a pass of the FP64 matrix-core
+counters per kernel (flops per launch and busy share).
 """
 from __future__ import annotations
 
@@ -43,19 +46,27 @@ def short_name(kernel: str) -> str:
     """Kernel class name as the launch timer reports it, from a mangled or
     demangled symbol: "k_gemm_f64<T,N>", "k_gemm_lds<N,N,64,32>",
     "k_qrcp_regs<8,6,12>", "k_chol_small", ..."""
-    m = re.search(r"(k_[a-z][a-z_0-9]*?)I((?:L[bi]\d+E)+)E", kernel)  # mangled template
+    m = re.search(r"(k_[a-z][a-z_0-9]*?)I((?:L[bi]\d+E)+)([df]*)E", kernel)  # mangled template
     if m:
         base = m.group(1)
         args = re.findall(r"L([bi])(\d+)E", m.group(2))
         vals = [("T" if v == "1" else "N") if t == "b" else v for t, v in args]
+        if m.group(3):
+            vals.append(m.group(3))  # operand element types, e.g. "ddd" or "ffd"
     else:
         m = re.search(r"(k_[a-z][a-z_0-9]*)<([^>]*)>", kernel)  # demangled template
         if m:
             base = m.group(1)
             vals = []
+            types = ""
             for a in m.group(2).split(","):
                 a = a.strip()
-                vals.append({"true": "T", "false": "N"}.get(a, a))
+                if a in ("double", "float"):
+                    types += a[0]
+                else:
+                    vals.append({"true": "T", "false": "N"}.get(a, a))
+            if types:
+                vals.append(types)
         else:
             m = re.search(r"(k_[a-z][a-z_0-9]*)", kernel)
             return m.group(1) if m else kernel.split("(")[0][:60]
@@ -82,15 +93,47 @@ def read_counter(dirpath: str, counter: str):
     return {k: list(v.values()) for k, v in per.items()}
 
 
+def mfma_summary(dirpath: str, simds: int = 1024) -> dict:
+    """Per kernel class: FP64 matrix-core flops per launch (SQ_INSTS_VALU_MFMA_MOPS_F64
+    counts 512 flops a unit) and the share of SIMD cycles the matrix cores were busy
+    while the kernel ran (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE x SIMDs)."""
+    mops = read_counter(dirpath, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+    busy = read_counter(dirpath, "SQ_VALU_MFMA_BUSY_CYCLES")
+    active = read_counter(dirpath, "GRBM_GUI_ACTIVE")
+    out = {}
+    for k in mops:
+        name = short_name(k)
+        if not name.startswith("k_"):
+            continue
+        rec = out.setdefault(name, {"dispatches": 0, "mfma_f64_flops": 0.0, "busy": 0.0, "active": 0.0})
+        rec["dispatches"] += len(mops[k])
+        rec["mfma_f64_flops"] += 512.0 * sum(mops[k])
+        rec["busy"] += sum(busy.get(k, []))
+        rec["active"] += sum(active.get(k, []))
+    for rec in out.values():
+        rec["mfma_f64_flops_per_launch"] = rec["mfma_f64_flops"] / max(rec["dispatches"], 1)
+        rec["mfma_busy_frac"] = rec["busy"] / (rec["active"] * simds) if rec["active"] > 0 else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--copy-mib", type=float, required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-mib", type=float)
     ap.add_argument("--workload", required=True)
     ap.add_argument("--command", required=True, help="command line the passes profiled")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--mfma", help="directory of a SQ_INSTS_VALU_MFMA_MOPS_F64 / SQ_VALU_MFMA_BUSY_CYCLES / "
+                                   "GRBM_GUI_ACTIVE pass: write its per-kernel summary instead")
     args = ap.parse_args()
+    if args.mfma:
+        rec = {"workload": args.workload, "source_sha256": source_digest(), "command": args.command,
+               "kernels": mfma_summary(args.mfma)}
+        with open(args.out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps({"kernels": len(rec["kernels"])}))
+        return
     fetch = read_counter(args.fetch, "FETCH_SIZE")
     write = read_counter(args.write, "WRITE_SIZE")
     copy_bytes = args.copy_mib * 2**20

@@ -171,3 +171,31 @@ def test_large_n_against_blocked_oracle(name, nb, tol):
         print(f"  gpu {out[2]!r} oracle {v['loglik']!r} |dl|={err:.3e} |dl|/n={err / n:.2e}", flush=True)
         assert plan.status(ws)["code"] == 0
         assert err <= fp64_bound(n, tol)
+
+
+def _compressed_cells():
+    jp = os.path.join(GOLDEN, "compressed_c2.json")
+    if not os.path.exists(jp):
+        return []
+    return [(r["cell"], r["nb"], r["tol"]) for r in json.load(open(jp)) if r["delta_c"] is not None]
+
+
+@pytest.mark.parametrize("cell,nb,tol", _compressed_cells())
+def test_smooth_cells_within_compression_bound(cell, nb, tol):
+    """nu = 3/2 datasets at n = 40,000 (ill-conditioned): l within
+    max(n max(1e-8, 0.1 tol), 10 |delta_c|), delta_c = l(Sigma~) - l(Sigma) from
+    the tile-truncated blocked oracle with the same tiles (Hilbert order)."""
+    rec = {(r["cell"], r["nb"], r["tol"]): r for r in json.load(open(os.path.join(GOLDEN, "compressed_c2.json")))}
+    dc = rec[(cell, nb, tol)]["delta_c"]
+    g, z = _golden(f"c2-{cell}")
+    ol, oz = _large_problem(g, z)
+    n = g["n"]
+    plan = B.Plan(n, nb, maxrank=nb // 2, dense_tiles=True)
+    ws = plan.workspace()
+    out = plan.loglik(ws, ol, oz, tuple(g["theta_true"]), tol).cpu().numpy()
+    err = abs(out[2] - g["values"][0]["loglik"])
+    bnd = max(n * max(1e-8, 0.1 * tol), 10 * abs(dc))
+    print(f"smooth cell {cell} nb={nb} tol={tol}: |dl|/n {err / n:.2e}, delta_c/n {dc / n:.2e}, "
+          f"bound/n {bnd / n:.2e}", flush=True)
+    assert plan.status(ws)["code"] == 0
+    assert err <= bnd
