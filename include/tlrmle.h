@@ -238,6 +238,38 @@ tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tl
                       void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Tukey g-and-h random fields (Section 4.2.2)                              */
+/* ------------------------------------------------------------------------ */
+
+/* T(s) = xi + omega tau(Z(s)), tau(z) = g^-1 (exp(g z) - 1) exp(h z^2 / 2)
+ * (g = 0: z exp(h z^2 / 2)), Z a standard Gaussian random field.  Valid
+ * parameters: xi, g finite, omega > 0, h >= 0 (tau is then increasing). */
+typedef struct {
+    double xi;
+    double omega;
+    double g;
+    double h;
+} tlr_tgh;
+
+/* d_z[i] = tau^-1((d_t[i] - xi) / omega), i < n: the Gaussian observation
+ * behind each TGH observation, in float64 (closed form when h = 0, else
+ * bracketed Newton iteration to a few ulps).  A value with no preimage
+ * (h = 0 and g (t - xi)/omega <= -1) or not finite gives NaN.  d_t and d_z
+ * may alias.  n = 0 is a no-op.  TLR_E_INVAL for invalid parameters. */
+tlr_status tlr_tgh_inverse(const double *d_t, int64_t n, tlr_tgh p, double *d_z, void *stream);
+
+/* TGH log-likelihood by the change of variables:
+ *     l_TGH = l(theta; z) - sum_i log(omega tau'(z_i)),  z = tlr_tgh_inverse(t),
+ * l(theta; z) the TLR Gaussian log-likelihood of tlr_loglik (theta of the
+ * Gaussian field: sigma2 = 1 for the standard field of the model).  d_t:
+ * ordered observations, n = the plan's n; d_z: out, n float64 (the
+ * transformed observations); d_out: out, 4 float64 on the device:
+ * {logdet, quad, l_TGH, sum_i log(omega tau'(z_i))}; l_TGH = -inf when the
+ * status is not OK or some observation has no preimage. */
+tlr_status tlr_loglik_tgh(tlr_plan plan, const double *d_locs, const double *d_t, tlr_theta theta, tlr_tgh p,
+                          double tol, void *d_ws, size_t ws_bytes, double *d_z, double *d_out, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Batched evaluation of independent problems                               */
 /* ------------------------------------------------------------------------ */
 

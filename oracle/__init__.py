@@ -15,6 +15,9 @@ paper by eye:
 * ``likelihood`` -- dense Gaussian log-likelihood (Section 1, eq. loglik).
 * ``tlr``        -- exact per-tile SVD ranks (Section 2 / Section 3 intro) and
                     the likelihood of the tile-truncated covariance.
+* ``blocked``    -- the dense likelihood by blocked Cholesky, for n up to 90,000.
+* ``tgh``        -- Tukey g-and-h random fields (Section 4.2.2): the transform,
+                    its inverse and the change-of-variables likelihood.
 
 Parity pins (see tests/test_oracle_*.py): closed forms and special cases of
 K_nu, brute-force determinants at high precision, an exact Markov
@@ -22,4 +25,4 @@ factorisation of the one-dimensional exponential model, the Hilbert curve
 orders printed in the paper's Hilbert figure, Table "memory" magnitudes, and
 structural invariants (bijections, permutation invariance, scaling laws).
 """
-from . import ordering, matern, likelihood, tlr  # noqa: F401
+from . import ordering, matern, likelihood, tlr, tgh  # noqa: F401

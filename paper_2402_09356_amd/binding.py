@@ -34,6 +34,10 @@ class _Theta(ctypes.Structure):
     _fields_ = [("sigma2", ctypes.c_double), ("beta", ctypes.c_double), ("nu", ctypes.c_double)]
 
 
+class _Tgh(ctypes.Structure):
+    _fields_ = [("xi", ctypes.c_double), ("omega", ctypes.c_double), ("g", ctypes.c_double), ("h", ctypes.c_double)]
+
+
 class KStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("exact_launches", ctypes.c_int64), ("exact_ms", ctypes.c_double), ("flops", ctypes.c_double),
@@ -67,6 +71,8 @@ _SIGNATURES = {
     "tlr_potrf": (I32, [P, P, SZ, P]),
     "tlr_solve_logdet": (I32, [P, P, P, SZ, P, P]),
     "tlr_loglik": (I32, [P, P, P, _Theta, F64, P, SZ, P, P, P]),
+    "tlr_tgh_inverse": (I32, [P, I64, _Tgh, P, P]),
+    "tlr_loglik_tgh": (I32, [P, P, P, _Theta, _Tgh, F64, P, SZ, P, P, P]),
     "tlr_batch_plan_create": (I32, [ctypes.POINTER(P), I32, P, P, I32, I32, U32]),
     "tlr_batch_plan_destroy": (None, [P]),
     "tlr_batch_ws_bytes": (SZ, [P]),
@@ -155,6 +161,16 @@ def reorder_noalloc(locs: torch.Tensor, kind: str, seed: int = 0, perm: torch.Te
     return perm
 
 
+def tgh_inverse(t: torch.Tensor, tgh, out: torch.Tensor | None = None) -> torch.Tensor:
+    """z = tau^-1((t - xi)/omega) for tgh = (xi, omega, g, h) (tlr_tgh_inverse)."""
+    if t.dtype != torch.float64 or t.dim() != 1:
+        raise ValueError("t must be a 1-D float64 tensor")
+    out = torch.empty_like(t) if out is None else out
+    _check(lib().tlr_tgh_inverse(_ptr(t), t.numel(), _Tgh(*map(float, tgh)), _ptr(out), _stream()),
+           "tlr_tgh_inverse")
+    return out
+
+
 def apply_perm(perm: torch.Tensor, locs: torch.Tensor, z: torch.Tensor | None = None, dequantize: bool = False):
     n = locs.shape[0]
     locs_out = torch.empty_like(locs)
@@ -226,6 +242,17 @@ class Plan:
         out = torch.empty(3, dtype=torch.float64, device=z.device) if out is None else out
         _check(lib().tlr_loglik(self._h, _ptr(locs), _ptr(z), _Theta(*map(float, theta)), float(tol), _ptr(ws),
                                 ws.numel(), _ptr(out), _ptr(ranks), _stream()), "tlr_loglik")
+        return out
+
+    def loglik_tgh(self, ws, locs, t, theta, tgh, tol, z=None, out=None):
+        """Tukey g-and-h log-likelihood (tlr_loglik_tgh): tgh = (xi, omega, g, h);
+        out = {logdet, quad, l_TGH, sum log(omega tau'(z))}, z the transformed
+        observations."""
+        z = torch.empty_like(t) if z is None else z
+        out = torch.empty(4, dtype=torch.float64, device=t.device) if out is None else out
+        _check(lib().tlr_loglik_tgh(self._h, _ptr(locs), _ptr(t), _Theta(*map(float, theta)),
+                                    _Tgh(*map(float, tgh)), float(tol), _ptr(ws), ws.numel(), _ptr(z), _ptr(out),
+                                    _stream()), "tlr_loglik_tgh")
         return out
 
     def tile(self, ws, i, j):

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtlrmle.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["order.hip", "gensolve.hip", "gemm.hip", "small.hip", "cholqr.hip", "peak.hip", "ktimer.cpp", "tlr.cpp",
+SOURCES = ["order.hip", "gensolve.hip", "gemm.hip", "small.hip", "cholqr.hip", "peak.hip", "tgh.hip", "ktimer.cpp", "tlr.cpp",
            "batch.cpp", "api.cpp"]
 
 # -packed-fp32-ops off: hand-written float code must not be lowered to packed

@@ -1,4 +1,5 @@
 // extern "C" entry points declared in include/tlrmle.h.
+#include <cmath>
 #include "kernels.h"
 #include "ktimer.h"
 
@@ -110,6 +111,37 @@ tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tl
     st = tlr::potrf(plan, d_ws, ws_bytes, s);
     if (st != TLR_OK) return st;
     return tlr::solve_logdet(plan, d_z, d_ws, ws_bytes, d_out, s);
+}
+
+static bool tgh_valid(const tlr_tgh &p) {
+    return std::isfinite(p.xi) && std::isfinite(p.g) && std::isfinite(p.omega) && p.omega > 0.0 &&
+           std::isfinite(p.h) && p.h >= 0.0;
+}
+
+tlr_status tlr_tgh_inverse(const double *d_t, int64_t n, tlr_tgh p, double *d_z, void *stream) {
+    if (n < 0 || !tgh_valid(p) || (n > 0 && (!d_t || !d_z))) return TLR_E_INVAL;
+    return tlr::tgh_inverse(d_t, n, p.xi, p.omega, p.g, p.h, d_z, as_stream(stream));
+}
+
+tlr_status tlr_loglik_tgh(tlr_plan plan, const double *d_locs, const double *d_t, tlr_theta theta, tlr_tgh p,
+                          double tol, void *d_ws, size_t ws_bytes, double *d_z, double *d_out, void *stream) {
+    hipStream_t s = as_stream(stream);
+    if (!plan || !d_locs || !d_t || !d_z || !d_ws || !d_out || !tgh_valid(p)) return TLR_E_INVAL;
+    int64_t n = 0;
+    int32_t nb = 0, nt = 0, maxrank = 0;
+    tlr::plan_shape(plan, &n, &nb, &nt, &maxrank);
+    // generation first: it checks theta and the workspace before any launch
+    tlr_status st = tlr::gen_tiles(plan, d_locs, theta, d_ws, ws_bytes, s);
+    if (st != TLR_OK) return st;
+    st = tlr::tgh_inverse(d_t, n, p.xi, p.omega, p.g, p.h, d_z, s);
+    if (st != TLR_OK) return st;
+    st = tlr::compress(plan, tol, d_ws, ws_bytes, nullptr, s);
+    if (st != TLR_OK) return st;
+    st = tlr::potrf(plan, d_ws, ws_bytes, s);
+    if (st != TLR_OK) return st;
+    st = tlr::solve_logdet(plan, d_z, d_ws, ws_bytes, d_out, s);
+    if (st != TLR_OK) return st;
+    return tlr::tgh_combine(d_z, n, p.omega, p.g, p.h, d_out, s);
 }
 
 tlr_status tlr_status_read(tlr_plan plan, const void *d_ws, tlr_devinfo *out, void *stream) {

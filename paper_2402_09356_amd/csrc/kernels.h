@@ -153,6 +153,12 @@ tlr_status logdet_quad(const double *diag, int nb, int nt, int64_t n, const doub
 tlr_status copy_panel(const double *src, int64_t lds, double *dst, int64_t ldd, int rows, const int32_t *cols_dev,
                       int max_cols, hipStream_t s);
 
+// Tukey g-and-h: z = tau^-1((t - xi)/omega) elementwise; then
+// out[3] = sum log(omega tau'(z_i)) and out[2] -= out[3] (-inf if not finite).
+tlr_status tgh_inverse(const double *t, int64_t n, double xi, double omega, double g, double h, double *z,
+                       hipStream_t s);
+tlr_status tgh_combine(const double *z, int64_t n, double omega, double g, double h, double *out, hipStream_t s);
+
 // Attainable peaks (measured): streaming copy bandwidth and FP64 MFMA rate.
 tlr_status peak_hbm(const void *src, void *dst, int64_t bytes, int reps, double *gbs, hipStream_t s);
 tlr_status peak_mfma_f64(double *scratch, int64_t scratch_words, int iters, double *tflops, hipStream_t s);

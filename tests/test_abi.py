@@ -73,6 +73,25 @@ def test_invalid_theta_and_small_workspace_rejected_on_host():
     assert L.tlr_loglik(None, fake, fake, ok, 1e-9, fake, 10, fake, None, None) == 1
 
 
+def test_tgh_argument_checks():
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    good = B._Tgh(0.0, 1.0, 0.3, 0.1)
+    for bad in (B._Tgh(0.0, 0.0, 0.3, 0.1), B._Tgh(0.0, 1.0, 0.3, -0.1), B._Tgh(float("nan"), 1.0, 0.3, 0.1),
+                B._Tgh(0.0, 1.0, float("inf"), 0.1)):
+        assert L.tlr_tgh_inverse(fake, 10, bad, fake, None) == 1
+    assert L.tlr_tgh_inverse(fake, -1, good, fake, None) == 1
+    assert L.tlr_tgh_inverse(None, 0, good, None, None) == 0
+    p = B.Plan(400, 100)
+    ok = B._Theta(1.0, 0.1, 0.5)
+    assert L.tlr_loglik_tgh(p._h, fake, fake, ok, B._Tgh(0.0, -1.0, 0.3, 0.1), 1e-9, fake, p.ws_bytes, fake, fake,
+                            None) == 1
+    # workspace and theta are checked before the transform is launched
+    assert L.tlr_loglik_tgh(p._h, fake, fake, ok, good, 1e-9, fake, 4096, fake, fake, None) == 2
+    assert L.tlr_loglik_tgh(p._h, fake, fake, B._Theta(1.0, -0.1, 0.5), good, 1e-9, fake, p.ws_bytes, fake, fake,
+                            None) == 1
+
+
 def test_reorder_argument_checks():
     L = B.lib()
     fake = ctypes.c_void_p(0x1000)
