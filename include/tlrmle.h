@@ -238,6 +238,38 @@ tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tl
                       void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Parsimonious bivariate Matern model (Section 4.2.1, eq. "bivmatern")      */
+/* ------------------------------------------------------------------------ */
+
+/* Two variables at the same n locations; one range a, marginal variances and
+ * smoothnesses, cross smoothness nu_12 = (nu_11 + nu_22)/2 and colocated
+ * correlation rho_12 = beta_12 sqrt(nu_11 nu_22) / nu_12 (the cited
+ * definition's Gamma ratios in two dimensions).  Valid for |beta_12| <= 1. */
+typedef struct {
+    double sigma2_11;
+    double sigma2_22;
+    double a;
+    double nu_11;
+    double nu_22;
+    double beta_12;
+} tlr_theta_biv;
+
+/* As tlr_gen_tiles for the 2n x 2n bivariate covariance.  The plan's n is the
+ * matrix size (even): d_locs holds n/2 ordered locations (n/2 x 2 AoS) and
+ * matrix entry 2p + v belongs to variable v (0 or 1) at location p.  The
+ * following tlr_compress / tlr_potrf / tlr_solve_logdet calls on the same
+ * workspace use this model.  TLR_E_INVAL for an odd n or an invalid theta. */
+tlr_status tlr_gen_tiles_bivariate(tlr_plan plan, const double *d_locs, tlr_theta_biv theta, void *d_ws,
+                                   size_t ws_bytes, void *stream);
+
+/* One bivariate evaluation: tlr_gen_tiles_bivariate -> compress -> potrf ->
+ * solve_logdet.  d_z: n observations, location-major (d_z[2p + v] = Z_v(s_p)).
+ * d_out, d_ranks as for tlr_loglik. */
+tlr_status tlr_loglik_bivariate(tlr_plan plan, const double *d_locs, const double *d_z, tlr_theta_biv theta,
+                                double tol, void *d_ws, size_t ws_bytes, double *d_out, int32_t *d_ranks,
+                                void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Tukey g-and-h random fields (Section 4.2.2)                              */
 /* ------------------------------------------------------------------------ */
 

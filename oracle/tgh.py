@@ -18,7 +18,8 @@ l_Gauss the Gaussian log-likelihood of Section 1 (eq. "loglik") and
     tau'(z) = exp(h z^2/2) (exp(g z) + h z (exp(g z) - 1) / g).
 
 tau^-1 has no closed form: it is taken here by plain bisection on a bracket
-grown until it holds the value (200 halvings, far past float64 resolution).
+grown until it holds the value, halved until it is an exact root or two
+adjacent floats (the closer of the two is returned).
 A value outside the range of tau (h = 0, g != 0: tau maps onto
 (-1/g, inf) or (-inf, -1/g)) has no preimage; its density is zero and the
 log-likelihood is -inf.  g = h = 0 gives the Gaussian field with mean xi and
@@ -43,7 +44,7 @@ def tau_prime(z, g: float, h: float):
     return np.exp(0.5 * h * z * z) * (np.exp(g * z) + h * z * core)
 
 
-def tau_inverse(y, g: float, h: float, halvings: int = 200):
+def tau_inverse(y, g: float, h: float, halvings: int = 2400):
     """z with tau(z) = y, elementwise, by bisection; NaN where y has no preimage."""
     if h < 0.0:
         raise ValueError("h must be >= 0 (tau is then increasing)")
@@ -62,12 +63,18 @@ def tau_inverse(y, g: float, h: float, halvings: int = 200):
             break
         lo = np.where(need_lo, 2.0 * lo, lo)
         hi = np.where(need_hi, 2.0 * hi, hi)
+    # halve until every bracket is an exact root or two adjacent floats
     for _ in range(halvings):
+        open_ = np.nextafter(lo, hi) < hi
+        if not open_.any():
+            break
         mid = 0.5 * (lo + hi)
-        up = tau(mid, g, h) < yy
-        lo = np.where(up, mid, lo)
-        hi = np.where(up, hi, mid)
-    out[ok] = 0.5 * (lo + hi)
+        tm = tau(mid, g, h)
+        hit = tm == yy
+        up = tm < yy
+        lo = np.where(open_ & (up | hit), mid, lo)
+        hi = np.where(open_ & (~up | hit), mid, hi)
+    out[ok] = np.where(tau(hi, g, h) - yy < yy - tau(lo, g, h), hi, lo)  # the closer end
     return out
 
 

@@ -34,6 +34,11 @@ class _Theta(ctypes.Structure):
     _fields_ = [("sigma2", ctypes.c_double), ("beta", ctypes.c_double), ("nu", ctypes.c_double)]
 
 
+class _ThetaBiv(ctypes.Structure):
+    _fields_ = [("sigma2_11", ctypes.c_double), ("sigma2_22", ctypes.c_double), ("a", ctypes.c_double),
+                ("nu_11", ctypes.c_double), ("nu_22", ctypes.c_double), ("beta_12", ctypes.c_double)]
+
+
 class _Tgh(ctypes.Structure):
     _fields_ = [("xi", ctypes.c_double), ("omega", ctypes.c_double), ("g", ctypes.c_double), ("h", ctypes.c_double)]
 
@@ -72,6 +77,8 @@ _SIGNATURES = {
     "tlr_solve_logdet": (I32, [P, P, P, SZ, P, P]),
     "tlr_loglik": (I32, [P, P, P, _Theta, F64, P, SZ, P, P, P]),
     "tlr_tgh_inverse": (I32, [P, I64, _Tgh, P, P]),
+    "tlr_gen_tiles_bivariate": (I32, [P, P, _ThetaBiv, P, SZ, P]),
+    "tlr_loglik_bivariate": (I32, [P, P, P, _ThetaBiv, F64, P, SZ, P, P, P]),
     "tlr_loglik_tgh": (I32, [P, P, P, _Theta, _Tgh, F64, P, SZ, P, P, P]),
     "tlr_batch_plan_create": (I32, [ctypes.POINTER(P), I32, P, P, I32, I32, U32]),
     "tlr_batch_plan_destroy": (None, [P]),
@@ -242,6 +249,16 @@ class Plan:
         out = torch.empty(3, dtype=torch.float64, device=z.device) if out is None else out
         _check(lib().tlr_loglik(self._h, _ptr(locs), _ptr(z), _Theta(*map(float, theta)), float(tol), _ptr(ws),
                                 ws.numel(), _ptr(out), _ptr(ranks), _stream()), "tlr_loglik")
+        return out
+
+    def loglik_bivariate(self, ws, locs, z, theta, tol, out=None, ranks=None):
+        """Bivariate Matern log-likelihood (tlr_loglik_bivariate): the plan's n
+        is 2 x the number of locations; theta = (sigma2_11, sigma2_22, a, nu_11,
+        nu_22, beta_12); z location-major (z[2p + v] = Z_v(s_p))."""
+        out = torch.empty(3, dtype=torch.float64, device=z.device) if out is None else out
+        _check(lib().tlr_loglik_bivariate(self._h, _ptr(locs), _ptr(z), _ThetaBiv(*map(float, theta)), float(tol),
+                                          _ptr(ws), ws.numel(), _ptr(out), _ptr(ranks), _stream()),
+               "tlr_loglik_bivariate")
         return out
 
     def loglik_tgh(self, ws, locs, t, theta, tgh, tol, z=None, out=None):

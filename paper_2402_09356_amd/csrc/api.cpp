@@ -9,6 +9,8 @@ void plan_destroy(tlr_plan p);
 size_t plan_ws_bytes(tlr_plan p);
 size_t plan_ws_bytes_budget(tlr_plan p, int64_t rank_budget);
 tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws, size_t ws_bytes, hipStream_t s);
+tlr_status gen_tiles_bivariate(tlr_plan p, const double *d_locs, const tlr_theta_biv &th, void *d_ws, size_t ws_bytes,
+                               hipStream_t s);
 tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks, hipStream_t s);
 tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s);
 tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_bytes, double *d_out, hipStream_t s);
@@ -105,6 +107,25 @@ tlr_status tlr_loglik(tlr_plan plan, const double *d_locs, const double *d_z, tl
     hipStream_t s = as_stream(stream);
     if (!plan || !d_locs || !d_z || !d_ws || !d_out) return TLR_E_INVAL;
     tlr_status st = tlr::gen_tiles(plan, d_locs, theta, d_ws, ws_bytes, s);
+    if (st != TLR_OK) return st;
+    st = tlr::compress(plan, tol, d_ws, ws_bytes, d_ranks, s);
+    if (st != TLR_OK) return st;
+    st = tlr::potrf(plan, d_ws, ws_bytes, s);
+    if (st != TLR_OK) return st;
+    return tlr::solve_logdet(plan, d_z, d_ws, ws_bytes, d_out, s);
+}
+
+tlr_status tlr_gen_tiles_bivariate(tlr_plan plan, const double *d_locs, tlr_theta_biv theta, void *d_ws,
+                                   size_t ws_bytes, void *stream) {
+    return tlr::gen_tiles_bivariate(plan, d_locs, theta, d_ws, ws_bytes, as_stream(stream));
+}
+
+tlr_status tlr_loglik_bivariate(tlr_plan plan, const double *d_locs, const double *d_z, tlr_theta_biv theta,
+                                double tol, void *d_ws, size_t ws_bytes, double *d_out, int32_t *d_ranks,
+                                void *stream) {
+    hipStream_t s = as_stream(stream);
+    if (!plan || !d_locs || !d_z || !d_ws || !d_out) return TLR_E_INVAL;
+    tlr_status st = tlr::gen_tiles_bivariate(plan, d_locs, theta, d_ws, ws_bytes, s);
     if (st != TLR_OK) return st;
     st = tlr::compress(plan, tol, d_ws, ws_bytes, d_ranks, s);
     if (st != TLR_OK) return st;

@@ -44,6 +44,25 @@ bool make_matern_const(double sigma2, double beta, double nu, MaternConst *out) 
     return true;
 }
 
+bool make_biv_const(double s11, double s22, double a, double nu11, double nu22, double beta12, BivConst *out) {
+    if (!std::isfinite(beta12) || !(std::fabs(beta12) <= 1.0)) return false;
+    const double nu12 = 0.5 * (nu11 + nu22);
+    BivConst b{};
+    if (!make_matern_const(s11, a, nu11, &b.m[0]) || !make_matern_const(s22, a, nu22, &b.m[2]) ||
+        !make_matern_const(1.0, a, nu12, &b.m[1]))
+        return false;
+    // colocated correlation of the cited parsimonious model in two
+    // dimensions: beta_12 sqrt(Gamma(nu11+1)/Gamma(nu11) Gamma(nu22+1)/Gamma(nu22))
+    // Gamma(nu12)/Gamma(nu12+1) = beta_12 sqrt(nu11 nu22) / nu12
+    const double rho = beta12 * std::sqrt(nu11 * nu22) / nu12;
+    const double scale = rho * std::sqrt(s11 * s22);
+    b.m[1].sigma2 = scale;
+    b.m[1].coef *= scale;
+    b.on = 1;
+    *out = b;
+    return true;
+}
+
 namespace {
 
 // One work-group per (tile, group of 8 columns): threads run down the rows,
@@ -105,6 +124,52 @@ __global__ __launch_bounds__(256) void k_gen_tiles(const GenDesc *__restrict__ d
             } else {
                 const double dx = x[gi] - xj, dy = y[gi] - yj;
                 v = matern_kind<KIND>(sqrt(dx * dx + dy * dy), c);
+            }
+            col[r] = v;
+        }
+    }
+}
+
+// C(d) of one function with its kind chosen at run time (the bivariate
+// generator mixes three functions in one tile).
+__device__ inline double matern_any(double d, const MaternConst &c) {
+    switch (c.kind) {
+        case 1: return matern_kind<1>(d, c);
+        case 2: return matern_kind<2>(d, c);
+        case 3: return matern_kind<3>(d, c);
+        default: return matern_kind<0>(d, c);
+    }
+}
+
+// Bivariate tiles: entry (gi, gj) of the 2n x 2n matrix is C_{v w}(|s_p - s_q|)
+// with p = gi / 2, v = gi % 2, q = gj / 2, w = gj % 2.  x, y hold the n
+// locations; `n` here is the matrix size 2n.
+__global__ __launch_bounds__(256) void k_gen_tiles_biv(const GenDesc *__restrict__ descs, int nb, int64_t n,
+                                                       const double *__restrict__ x, const double *__restrict__ y,
+                                                       BivConst bc) {
+    const GenDesc d = descs[blockIdx.y];
+    const int q0 = blockIdx.x * 8;
+    for (int q = q0; q < q0 + 8 && q < nb; ++q) {
+        const int64_t gj = d.col0 + q;
+        const bool jin = gj < n;
+        const int64_t pj = gj >> 1;
+        const int wj = (int)(gj & 1);
+        const double xj = jin ? x[pj] : 0.0, yj = jin ? y[pj] : 0.0;
+        double *col = d.dst + (int64_t)q * d.ld;
+        for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+            const int64_t gi = d.row0 + r;
+            double v;
+            if (gi >= n || !jin) {
+                v = (gi == gj) ? 1.0 : 0.0;  // identity padding of the ragged last tile
+            } else {
+                const MaternConst &c = bc.m[(int)(gi & 1) + wj];
+                const int64_t pi = gi >> 1;
+                if (pi == pj) {
+                    v = c.sigma2;  // colocated: the variance, or rho_12 sigma_11 sigma_22
+                } else {
+                    const double dx = x[pi] - xj, dy = y[pi] - yj;
+                    v = matern_any(sqrt(dx * dx + dy * dy), c);
+                }
             }
             col[r] = v;
         }
@@ -363,6 +428,17 @@ tlr_status gen_tiles_launch(const GenDesc *d_descs, int count, int nb, int64_t n
         case 3: hipLaunchKernelGGL(k_gen_tiles<3>, grid, block, 0, s, d_descs, nb, n, x, y, c); break;
         default: hipLaunchKernelGGL(k_gen_tiles<0>, grid, block, 0, s, d_descs, nb, n, x, y, c); break;
     }
+    TLR_HIP(hipGetLastError());
+    return TLR_OK;
+}
+
+tlr_status gen_tiles_biv_launch(const GenDesc *d_descs, int count, int nb, int64_t n, const double *x,
+                                const double *y, const BivConst &c, hipStream_t s) {
+    if (count <= 0) return TLR_OK;
+    static const int cls = ktimer_class("k_gen_tiles");
+    KTimer kt(cls, s, 0.0, 8.0 * (double)nb * nb * count, true);
+    const dim3 grid((unsigned)cdiv(nb, 8), count), block(256);
+    hipLaunchKernelGGL(k_gen_tiles_biv, grid, block, 0, s, d_descs, nb, n, x, y, c);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }

@@ -119,6 +119,9 @@ tlr_status gen_tiles_launch(const GenDesc *d_descs, int count, int nb, int64_t n
 // Per-theta table for general nu (kChebPieces * (kChebDeg+1) doubles at tab);
 // sets c->tab (left null for the closed forms).
 tlr_status build_knu_table(MaternConst *c, double *tab, hipStream_t s);
+// Bivariate model: n is the matrix size (twice the number of locations in x, y).
+tlr_status gen_tiles_biv_launch(const GenDesc *d_descs, int count, int nb, int64_t n, const double *x,
+                                const double *y, const BivConst &c, hipStream_t s);
 
 // Misc.
 tlr_status gaussian_fill(double *out, int64_t count, uint64_t seed, hipStream_t s);

@@ -38,6 +38,17 @@ struct MaternConst {
     int nint;
 };
 
+// Parsimonious bivariate Matern model (paper Section 4.2.1, eq. "bivmatern"):
+// the three functions C_11, C_12, C_22 as univariate Matern constants (one
+// range a; nu_12 = (nu_11 + nu_22)/2; the variance field of C_12 is
+// rho_12 sigma_11 sigma_22, which may be zero or negative).  Matrix entry
+// 2p + v is variable v at location p; on = 0 for the univariate model.
+struct BivConst {
+    MaternConst m[3];  // C_11, C_12, C_22 (index v + w)
+    int32_t on;
+    int32_t pad;
+};
+
 constexpr int kChebDeg = 10;
 constexpr int kChebPieces = 160;
 constexpr double kTabXlo = 1e-6;
@@ -45,6 +56,10 @@ constexpr double kTabXhi = 745.0;
 
 // Host: constants of one theta.  Returns false for invalid theta.
 bool make_matern_const(double sigma2, double beta, double nu, MaternConst *out);
+// Host: the three functions of a bivariate theta (tables not yet attached).
+// False for invalid theta (a variance, the range or a smoothness not
+// positive, |beta_12| > 1, anything not finite).
+bool make_biv_const(double s11, double s22, double a, double nu11, double nu22, double beta12, BivConst *out);
 
 __device__ inline void temme_k(double mu, double x, const MaternConst &c, double *kmu, double *kmu1) {
     const double L = log(2.0 / x);

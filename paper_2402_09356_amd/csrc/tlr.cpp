@@ -55,6 +55,7 @@ constexpr int kMaxWave = 4096;  // tile jobs per batched launch sequence
 struct ParamsBlock {
     DevParams dp;
     MaternConst mc;
+    BivConst bv;  // bv.on: the bivariate model's generator replaces mc's
     uint64_t hint_magic;
     double tol;
 };
@@ -890,7 +891,7 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->off_wide = p->dense_ok ? take(sizeof(double) * 2 * (size_t)nb * nb * (size_t)std::max<int64_t>(p->ntiles, 1)) : 0;
     p->off_yvec = take(sizeof(double) * p->npad);
     p->off_omega = take(sizeof(double) * (size_t)nb * p->kmax);
-    p->off_knu = take(sizeof(double) * kChebPieces * (kChebDeg + 1));
+    p->off_knu = take(sizeof(double) * 3 * kChebPieces * (kChebDeg + 1));  // three for the bivariate model
     // descriptors of one wave: about 42 (GEMM and small-kernel descriptors,
     // ~100 bytes each) per job of a full kMaxWave-job wave, plus the
     // per-column products of the factorisation
@@ -968,6 +969,45 @@ tlr_status gen_tiles(tlr_plan p, const double *d_locs, tlr_theta th, void *d_ws,
     return TLR_OK;
 }
 
+// The parsimonious bivariate Matern model: the plan's n is the matrix size,
+// twice the number of locations; entry 2p + v is variable v at location p.
+tlr_status gen_tiles_bivariate(tlr_plan p, const double *d_locs, const tlr_theta_biv &th, void *d_ws, size_t ws_bytes,
+                               hipStream_t s) {
+    if (!p || !d_locs || !d_ws || p->n % 2 != 0) return TLR_E_INVAL;
+    if (ws_bytes < p->off_fac) return TLR_E_NOMEM;
+    BivConst bc{};
+    if (!make_biv_const(th.sigma2_11, th.sigma2_22, th.a, th.nu_11, th.nu_22, th.beta_12, &bc)) return TLR_E_INVAL;
+    Ctx c(p, d_ws, s);
+    double *tabs = reinterpret_cast<double *>(c.ws + p->off_knu);
+    for (int q = 0; q < 3; ++q) TLR_TRY(build_knu_table(&bc.m[q], tabs + (size_t)q * kChebPieces * (kChebDeg + 1), s));
+    ParamsBlock hb{};
+    TLR_HIP(hipMemcpyAsync(&hb, c.pblock(), sizeof(ParamsBlock), hipMemcpyDeviceToHost, s));
+    TLR_HIP(hipStreamSynchronize(s));
+    const uint64_t keep_magic = hb.hint_magic;
+    hb = ParamsBlock{};
+    // the larger variance bounds every tile's norm (nb sigma2), as in the
+    // univariate model: the range finder's pass rule reads it
+    hb.dp.sigma2 = std::max(th.sigma2_11, th.sigma2_22);
+    hb.dp.beta = th.a;
+    hb.dp.nu = std::min(th.nu_11, th.nu_22);
+    hb.dp.status = 0;
+    hb.dp.fail_i = hb.dp.fail_j = -1;
+    hb.dp.dense_ok = p->dense_ok ? 1 : 0;
+    hb.dp.floor_rel = p->mixed ? 2.0 * 0x1.0p-24 : 0.0;
+    hb.mc = bc.m[0];
+    hb.bv = bc;
+    hb.hint_magic = keep_magic;
+    TLR_HIP(hipMemcpyAsync(c.pblock(), &hb, sizeof(ParamsBlock), hipMemcpyHostToDevice, s));
+    TLR_TRY(split_locs(d_locs, p->n / 2, p->npad, c.x(), c.y(), s));
+    std::vector<GenDesc> g;
+    for (int k = 0; k < p->nt; ++k) g.push_back(GenDesc{c.diag(k), k * p->nb, k * p->nb, p->nb, 1});
+    TLR_PUSH(dg, c, g);
+    TLR_LAUNCH(c, gen_tiles_biv_launch(dg, (int)g.size(), p->nb, p->n, c.x(), c.y(), bc, s));
+    TLR_TRY(gaussian_fill(c.omega(), (int64_t)p->nb * p->kmax, kSketchSeed, s));
+    TLR_HIP(hipStreamSynchronize(s));  // host descriptors above go out of scope
+    return TLR_OK;
+}
+
 // ------------------------------------------------------------ compression --
 
 tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t *d_ranks, hipStream_t s) {
@@ -988,6 +1028,7 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
     // evaluations), so the result depends on the inputs only.
     const bool hints_ok = false;
     const MaternConst mc = hb.mc;
+    const BivConst bv = hb.bv;
     {
         double t = tol;
         TLR_HIP(hipMemcpyAsync(&c.pblock()->tol, &t, sizeof(double), hipMemcpyHostToDevice, s));
@@ -1035,7 +1076,10 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
                 if (jobs.size() >= (size_t)kMaxWave) break;
             }
             TLR_PUSH(dg, c, gens);
-            TLR_LAUNCH(c, gen_tiles_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), mc, s));
+            if (bv.on)
+                TLR_LAUNCH(c, gen_tiles_biv_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), bv, s));
+            else
+                TLR_LAUNCH(c, gen_tiles_launch(dg, (int)gens.size(), nb, p->n, c.x(), c.y(), mc, s));
             TLR_TRY(rsvd(c, jobs, tol, nullptr, 0, p->svd_trunc, q1_passes(p, hb.dp.sigma2, tol),
                          full_passes(p, hb.dp.sigma2, tol)));
             Ctx::StatRead sr;

@@ -29,7 +29,7 @@ def test_inverse_against_oracle(g, h):
     z = 2.5 * synthetic.standard_normal(n, synthetic.seed_for(8, synthetic.SEED_Z))
     xi, omega = 0.3, 1.7
     t = OG.sample_tgh(z, xi, omega, g, h)
-    t[:4] = [xi, xi + 1e-300, xi - 1e-12, xi + 5.0]
+    t[:4] = [xi, xi + 1e-13, xi - 1e-12, xi + 5.0]
     if h == 0.0 and g != 0.0:
         t[4] = xi - 2.0 * omega / g  # below (g > 0) or above (g < 0) the range: no preimage
     got = B.tgh_inverse(to_dev(t), (xi, omega, g, h)).cpu().numpy()
