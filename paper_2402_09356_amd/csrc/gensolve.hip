@@ -214,32 +214,43 @@ __device__ inline double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// y <- L^-1 y for one dense lower-triangular nb x nb tile (one work-group),
-// 64 rows at a time: the diagonal block is staged in LDS and solved by one
-// wave (lane r holds y_r; the solved entry, y_r times the reciprocal of the
-// diagonal entry, is broadcast with readlane), then
-// every thread updates rows below from the block's columns.
-__global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L, int nb,
-                                                   double *__restrict__ yv, const DevParams *params) {
+// y <- L^-1 y for one dense lower-triangular nb x nb tile (one work-group of
+// sixteen waves), 64 rows at a time: the diagonal block is staged in LDS and
+// solved by one wave (lane r holds y_r; the solved entry, y_r times the
+// reciprocal of the diagonal entry, is broadcast with readlane); then the rows
+// below take the block's columns.  The work-group is one compute unit reading
+// the whole lower triangle, so the update keeps as much of it in flight as
+// the registers allow: thread t takes column quarter t / 256 (16 columns) of
+// rows t % 256 + 256 k, eight columns at a time (32 loads in flight), and the
+// four quarters' partial sums meet in LDS in a fixed order.  The next
+// diagonal block is loaded during the update.
+constexpr int kTrsvThreads = 1024, kTrsvRowLanes = 256, kTrsvRowsPerLane = 4;
+
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv_tile(const double *__restrict__ L, int nb,
+                                                            double *__restrict__ yv, const DevParams *params) {
     __shared__ double Db[64 * 65];
     __shared__ double xb[64];
+    __shared__ double part[4][kTrsvRowLanes * kTrsvRowsPerLane];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (params->status != 0) return;
+    const int cq = tid / kTrsvRowLanes, rl = tid % kTrsvRowLanes;
+    // the diagonal block of b0: four entries a thread
+    double dv[4];
+    auto load_diag = [&](int b0) {
+        const int bs = (nb - b0 < 64) ? nb - b0 : 64;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + kTrsvThreads * u, r = e & 63, c = e >> 6;
+            dv[u] = (r < bs && c < bs && r >= c) ? L[(b0 + r) + (int64_t)(b0 + c) * nb] : 0.0;
+        }
+    };
+    load_diag(0);
     for (int b0 = 0; b0 < nb; b0 += 64) {
         const int bs = (nb - b0 < 64) ? nb - b0 : 64;
-        {
-            // sixteen loads a thread, all in flight together
-            double v[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int e = tid + 256 * u, r = e & 63, c = e >> 6;
-                v[u] = (r < bs && c < bs && r >= c) ? L[(b0 + r) + (int64_t)(b0 + c) * nb] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int e = tid + 256 * u, r = e & 63, c = e >> 6;
-                Db[r + 65 * c] = v[u];
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + kTrsvThreads * u, r = e & 63, c = e >> 6;
+            Db[r + 65 * c] = dv[u];
         }
         __syncthreads();
         if (wave == 0) {
@@ -256,31 +267,36 @@ __global__ __launch_bounds__(256) void k_trsv_tile(const double *__restrict__ L,
             if (lane < bs) yv[b0 + lane] = v;
         }
         __syncthreads();
-        // rows below the block: four rows a thread and eight columns at a
-        // time, so thirty-two loads are in flight together
-        for (int row0 = b0 + bs + tid; row0 < nb; row0 += 4 * 256) {
-            double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-            for (int c = 0; c < bs; c += 8) {
-                double lv[4][8];
+        if (b0 + 64 < nb) load_diag(b0 + 64);  // in flight during the update below
+        // rows below the block, in chunks of 1024 rows
+        for (int base = b0 + bs; base < nb; base += kTrsvRowLanes * kTrsvRowsPerLane) {
+            double acc[kTrsvRowsPerLane] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+            for (int h = 0; h < 2; ++h) {
+                const int c0 = 16 * cq + 8 * h;
+                double lv[kTrsvRowsPerLane][8];
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
+                for (int k = 0; k < kTrsvRowsPerLane; ++k)
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        const int row = row0 + 256 * k;
-                        lv[k][u] = (row < nb && c + u < bs) ? L[row + (int64_t)(b0 + c + u) * nb] : 0.0;
+                        const int row = base + rl + kTrsvRowLanes * k;
+                        lv[k][u] = (row < nb && c0 + u < bs) ? L[row + (int64_t)(b0 + c0 + u) * nb] : 0.0;
                     }
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
+                for (int k = 0; k < kTrsvRowsPerLane; ++k)
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) acc[k][u & 1] += lv[k][u] * xb[(c + u) & 63];
+                    for (int u = 0; u < 8; ++u) acc[k] += lv[k][u] * xb[c0 + u];
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int row = row0 + 256 * k;
-                if (row < nb) yv[row] -= acc[k][0] + acc[k][1];
+            for (int k = 0; k < kTrsvRowsPerLane; ++k) part[cq][rl + kTrsvRowLanes * k] = acc[k];
+            __syncthreads();
+            {
+                const int row = base + tid;
+                if (tid < kTrsvRowLanes * kTrsvRowsPerLane && row < nb)
+                    yv[row] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -495,7 +511,7 @@ tlr_status trsv_tile(const double *L, int nb, double *yv, const DevParams *param
     static const int cls = ktimer_class("k_trsv_tile");
     const double b = nb;
     KTimer kt(cls, s, b * b, 8.0 * (b * (b + 1.0) / 2.0 + 2.0 * b), true);
-    hipLaunchKernelGGL(k_trsv_tile, dim3(1), dim3(256), 0, s, L, nb, yv, params);
+    hipLaunchKernelGGL(k_trsv_tile, dim3(1), dim3(kTrsvThreads), 0, s, L, nb, yv, params);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }

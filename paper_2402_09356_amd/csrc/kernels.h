@@ -76,7 +76,8 @@ tlr_status jacobi_svd(const SmallDesc *d_descs, int count, int max_k, double tol
 // Y = B^T (k x r) with A ~ Q1 B; R = k x k scratch (when k is too large for LDS).
 // flag = 1 (rank 0 written) when k - r < min_tail and k < k_full.
 tlr_status qrcp_trunc(const SmallDesc *d_descs, int count, int max_k, double tol, int min_tail, int k_full,
-                      int rank_cap, DevParams *params, hipStream_t s);
+                      int rank_cap, DevParams *params, hipStream_t s,
+                      int min_k = 1);
 
 // Dense diagonal-tile kernels (nb x nb, column-major, ld = nb).
 // Blocked Cholesky (block 64): the trailing updates use ceil(nb/64) GEMM

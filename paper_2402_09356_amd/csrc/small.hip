@@ -359,8 +359,11 @@ __device__ void qrcp_trunc(double *M, int ld, int k, double tol2, double *cn, do
 // group g owns columns g + 4 NW cc (cc < CPG), its lane s the rows s + 16 rr
 // (rr < RPS), so a column's reductions are four DPP steps inside its group.
 // Columns are never swapped: the pivot of step c is frozen in place (rows < c
-// hold its column of R, row c the diagonal alpha_c) and its Householder
-// vector is kept in V (k x k scratch, column c).  Same arithmetic as
+// hold its column of R, row c the diagonal alpha_c, rows below c its
+// Householder vector, whose first entry is kept aside).  Each step the owner
+// group puts the pivot column in LDS and every group forms the reflector
+// itself; the reflectors go to V (k x k scratch, column c) once, after the
+// last step.  Same arithmetic as
 // qrcp_trunc (pivot = largest remaining norm, smallest index on ties; stop
 // when the remaining Frobenius norm is <= tol), so Y = B^T comes straight from
 // the registers and Q1 is accumulated in registers from V.  The column norms
@@ -375,6 +378,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
     __shared__ int pst[KC];  // step at which the column was pivoted (kNever: not yet)
     __shared__ double vsh[KR];
     __shared__ double bet[KR];
+    __shared__ double v0s[KR];  // first entry of each step's Householder vector
     __shared__ double redv[2][2 * NW];  // per wave: trailing norm, best norm; by step parity
     __shared__ int redi[2][NW];
     const SmallDesc d = descs[blockIdx.x];
@@ -484,26 +488,9 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
         rem = readlane_d(rem, 0);
         if (c == 0) tol2 = trunc_thr2(params, d.noise, rem, tol2);
         if (rem <= tol2) break;
-        // Householder vector of column bj, by the group that owns it
+        // the pivot column (rows c .. k-1) into LDS, by the group that owns it
         if (grp == bj % G) {
             const int oc = bj / G;
-            double x2 = 0.0, x0 = 0.0;
-#pragma unroll
-            for (int cc = 0; cc < CPG; ++cc)
-                if (cc == oc) {
-#pragma unroll
-                    for (int rr = 0; rr < RPS; ++rr) {
-                        const int i = sl + 16 * rr;
-                        if (i == c) x0 = a[cc][rr];
-                        if (i > c && i < k) x2 += a[cc][rr] * a[cc][rr];
-                    }
-                }
-            x2 = red16(x2);
-            x0 = red16(x0);
-            const double nrm = sqrt(x0 * x0 + x2);
-            const double alpha = (x0 > 0.0) ? -nrm : nrm;
-            const double v0 = x0 - alpha;
-            const double vtv = v0 * v0 + x2;
 #pragma unroll
             for (int cc = 0; cc < CPG; ++cc)
                 if (cc == oc) {
@@ -511,26 +498,50 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
 #pragma unroll
                     for (int rr = 0; rr < RPS; ++rr) {
                         const int i = sl + 16 * rr;
-                        const double vi = (i < c || i >= k) ? 0.0 : ((i == c) ? v0 : a[cc][rr]);
-                        vsh[i] = vi;
-                        if (i < k) V[i + (int64_t)c * k] = vi;
-                        if (i == c) a[cc][rr] = alpha;
+                        vsh[i] = (i < c || i >= k) ? 0.0 : a[cc][rr];
                     }
                 }
-            if (sl == 0) {
-                bet[c] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-                pst[bj] = c;
-            }
+            if (sl == 0) pst[bj] = c;
         }
         __syncthreads();
-        const double bta = bet[c];
+        // every group forms the Householder vector v = x - alpha e_c of the
+        // shared column, each with the sums its owner would form (the same
+        // terms in the same order), so every lane holds the same values
+        double vr[RPS];
+        double x2 = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < RPS; ++rr) {
+            vr[rr] = vsh[sl + 16 * rr];
+            if (sl + 16 * rr > c) x2 += vr[rr] * vr[rr];
+        }
+        x2 = red16(x2);
+        const double x0 = vsh[c];
+        const double nrm = sqrt(x0 * x0 + x2);
+        const double alpha = (x0 > 0.0) ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        const double vtv = v0 * v0 + x2;
+        const double bta = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < RPS; ++rr)
+            if (sl + 16 * rr == c) vr[rr] = v0;
+        if (grp == bj % G) {  // R's diagonal entry replaces x_c in the frozen column
+            const int oc = bj / G;
+#pragma unroll
+            for (int cc = 0; cc < CPG; ++cc)
+                if (cc == oc) {
+#pragma unroll
+                    for (int rr = 0; rr < RPS; ++rr)
+                        if (sl + 16 * rr == c) a[cc][rr] = alpha;
+                }
+        }
+        if (tid == 0) {
+            bet[c] = bta;
+            v0s[c] = v0;
+        }
         // row blocks wholly above row c are finished: the reflector is zero
         // there, so they are skipped (one uniform branch per block; the terms
         // left out are exact zeros, so every sum keeps its bits)
         const int rb0 = c >> 4;
-        double vr[RPS];
-#pragma unroll
-        for (int rr = 0; rr < RPS; ++rr) vr[rr] = vsh[sl + 16 * rr];
         double w[CPG];
 #pragma unroll
         for (int cc = 0; cc < CPG; ++cc) w[cc] = 0.0;
@@ -580,6 +591,21 @@ __global__ __launch_bounds__(NW * 64) void k_qrcp_regs(const SmallDesc *__restri
             for (int rr = 0; rr < RPS; ++rr) {
                 const int i = sl + 16 * rr;
                 if (i < r) d.Y[p + (int64_t)i * d.ldy] = (i <= ps) ? a[cc][rr] : 0.0;
+            }
+        }
+    }
+    __syncthreads();  // v0s and pst of the last step visible to every wave
+    // the reflectors into V: the column pivoted at step h holds v below row h
+    // (frozen since), and v_h was kept aside
+#pragma unroll
+    for (int cc = 0; cc < CPG; ++cc) {
+        const int p = grp + G * cc;
+        const int h = (p < k) ? pst[p] : kNever;
+        if (h < rr_rank) {
+#pragma unroll
+            for (int rr = 0; rr < RPS; ++rr) {
+                const int i = sl + 16 * rr;
+                if (i >= h && i < k) V[i + (int64_t)h * k] = (i == h) ? v0s[h] : a[cc][rr];
             }
         }
     }
@@ -861,17 +887,18 @@ tlr_status jacobi_svd(const SmallDesc *d_descs, int count, int max_k, double tol
 }
 
 tlr_status qrcp_trunc(const SmallDesc *d_descs, int count, int max_k, double tol, int min_tail, int k_full,
-                      int rank_cap, DevParams *params, hipStream_t s) {
+                      int rank_cap, DevParams *params, hipStream_t s, int min_k) {
     if (count <= 0) return TLR_OK;
     static const int cls_s = ktimer_class("k_qrcp_regs<4,4,4>"), cls_m = ktimer_class("k_qrcp_regs<8,6,12>"),
                      cls_t = ktimer_class("k_qrcp_trunc");
-    // the stopping step (the rank) is decided on the device: no fixed count
-    {
+    // the stopping step (the rank) is decided on the device: no fixed count.
+    // min_k: no descriptor is narrower (the kernels for narrower k are skipped)
+    if (min_k <= kQrSmallK) {
         KTimer kt(cls_s, s, 0.0, 0.0, false);
         hipLaunchKernelGGL((k_qrcp_regs<4, 4, 4>), dim3(count), dim3(256), 0, s, d_descs, tol, min_tail, k_full,
                            rank_cap, params, 1);
     }
-    if (max_k > kQrSmallK) {
+    if (max_k > kQrSmallK && min_k <= kQrMidK) {
         KTimer kt(cls_m, s, 0.0, 0.0, false);
         hipLaunchKernelGGL((k_qrcp_regs<8, 6, 12>), dim3(count), dim3(512), 0, s, d_descs, tol, min_tail, k_full,
                            rank_cap, params, kQrSmallK + 1);

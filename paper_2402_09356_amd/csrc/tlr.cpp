@@ -20,6 +20,7 @@
 //             host as ranks become known (first fit at the fill mark; a
 //             recompressed tile reuses its slot when the new rank fits)
 #include <algorithm>
+#include <functional>
 #include <climits>
 #include <cmath>
 #include <cstdlib>
@@ -692,8 +693,13 @@ int full_passes(const tlr_plan_s *p, double sigma2, double tol) {
     return p->mixed ? 3 : 4;
 }
 
+constexpr int kQrSmallSketch = 64;  // widest sketch of the small register QRCP kernel
+
+// `after_first`: called once the first product of the range finder is
+// queued (the factorisation issues the diagonal tile's Cholesky on the second
+// stream there, ahead of this function's own use of that stream).
 tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int Rj, bool exact_svd,
-                int passes_q1, int passes_full) {
+                int passes_q1, int passes_full, const std::function<tlr_status()> *after_first = nullptr) {
     if (jobs.empty()) return TLR_OK;
     // widest sample first: its work-groups, the longest, are dispatched
     // first in every batched launch below (the order of the results is not
@@ -703,6 +709,7 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int 
     int kmx = 0;
     for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
     TLR_TRY(apply_op(c, jobs, false, true, false, Yj, Rj));   // Yb = T W
+    if (after_first) TLR_TRY((*after_first)());
     TLR_TRY(cholqr(c, jobs, false, false, passes_q1));       // Yb = Q1 (only its span is used)
     TLR_TRY(apply_op(c, jobs, true, false, true, Yj, Rj));    // Zb = T^T Q1
     TLR_TRY(cholqr(c, jobs, true, false, passes_full, passes_full == 3 ? 1 : 2));   // Zb = Q2
@@ -729,8 +736,26 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int 
             d.noise = jb.noise;
             sq.push_back(d);
         }
-        TLR_PUSH(dsq, c, sq);
-        TLR_LAUNCH(c, qrcp_trunc(dsq, (int)sq.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s));
+        // sketches of up to 64 columns take the small register kernel, wider
+        // ones the larger kernels: when a wave has both, the narrow ones run
+        // on the second stream beside the wide ones (a wave is ordered widest
+        // first, so the narrow ones form the tail of the list)
+        size_t nw = 0;
+        while (nw < sq.size() && sq[nw].k > kQrSmallSketch) ++nw;
+        if (nw > 0 && nw < sq.size()) {
+            TLR_PUSH(dsq, c, sq);
+            TLR_TRY(c.flush());
+            hipStream_t ss = c.fork();
+            TLR_TRY(qrcp_trunc(dsq + nw, (int)(sq.size() - nw), kQrSmallSketch, tol, c.p->min_tail, c.p->kmax,
+                               c.p->rcap, c.params(), ss));
+            TLR_TRY(qrcp_trunc(dsq, (int)nw, kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s,
+                               kQrSmallSketch + 1));
+            TLR_TRY(c.join());
+        } else {
+            TLR_PUSH(dsq, c, sq);
+            TLR_LAUNCH(c, qrcp_trunc(dsq, (int)sq.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(),
+                                     c.s));
+        }
         std::vector<GemmDesc> gu2, gv2;
         for (auto &jb : jobs) {
             GemmDesc a = gd(jb.Yb, nb, jb.Xs, jb.k, jb.Uout, nb, nb, 0, jb.k, 1.0, 0.0);
@@ -1249,7 +1274,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             side_s = c.fork();
         }
         bool diag_issued = false;
-        auto issue_diag = [&]() -> tlr_status {
+        const std::function<tlr_status()> issue_diag = [&]() -> tlr_status {
             if (diag_issued) return TLR_OK;
             diag_issued = true;
             return potrf_tile(c.diag(j), nb, j, c.params(), dpd, side_s);
@@ -1370,7 +1395,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                     }
                     if (!jobs.empty())
                         TLR_TRY(rsvd(c, jobs, tol, Yj, Rj, p->svd_trunc, q1_passes(p, hb.dp.sigma2, tol),
-                                     full_passes(p, hb.dp.sigma2, tol)));
+                                     full_passes(p, hb.dp.sigma2, tol), &issue_diag));
                     TLR_TRY(issue_diag());
                     Ctx::StatRead sr;
                     TLR_TRY(c.read_stats(jobs, sr));
