@@ -79,14 +79,18 @@ class PinnedPool {
   public:
     char *get(size_t bytes, size_t *cap) {
         {
+            // the smallest free buffer that fits
             std::lock_guard<std::mutex> g(mu_);
+            size_t best = free_.size();
             for (size_t i = 0; i < free_.size(); ++i)
-                if (free_[i].second >= bytes) {
-                    auto b = free_[i];
-                    free_.erase(free_.begin() + (std::ptrdiff_t)i);
-                    *cap = b.second;
-                    return b.first;
-                }
+                if (free_[i].second >= bytes && (best == free_.size() || free_[i].second < free_[best].second))
+                    best = i;
+            if (best < free_.size()) {
+                auto b = free_[best];
+                free_.erase(free_.begin() + (std::ptrdiff_t)best);
+                *cap = b.second;
+                return b.first;
+            }
         }
         void *h = nullptr;
         if (hipHostMalloc(&h, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
