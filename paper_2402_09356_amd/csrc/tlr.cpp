@@ -38,7 +38,7 @@ struct tlr_plan_s {
     tlr_precision prec;
     uint32_t flags;
     size_t off_params, off_x, off_y, off_diag, off_rsig, off_rL, off_tstat, off_tofs, off_yvec, off_omega,
-        off_desc, off_arena, off_knu, off_dense, off_wide, off_nrm_s, off_nrm_l, off_noise, off_fac;
+        off_desc, off_arena, off_knu, off_dense, off_wide, off_nrm_s, off_nrm_l, off_noise, off_linv, off_fac;
     bool mixed;  // TLR_MIXED_FP32: low-rank factors stored in float32
     int fw;      // bytes per stored factor entry (8, or 4 when mixed)
     bool dense_ok;   // TLR_PLAN_DENSE_TILES: over-rank tiles kept dense in the wide slots
@@ -187,6 +187,7 @@ struct Ctx {
             side_pool().put(side);
         }
         if (hdesc_pageable.empty() && hdesc) pinned_pool().put(hdesc, hdesc_cap);
+        if (hstat_pageable.empty() && hstat) pinned_pool().put(reinterpret_cast<char *>(hstat), hstat_cap);
     }
     // A second stream for work that may run beside the main stream's (the
     // dense Cholesky of a diagonal tile beside the recompression of the tiles
@@ -309,6 +310,7 @@ struct Ctx {
     double *nrm_s() const { return reinterpret_cast<double *>(ws + p->off_nrm_s); }
     double *nrm_l() const { return reinterpret_cast<double *>(ws + p->off_nrm_l); }
     double *noise(int64_t t) const { return reinterpret_cast<double *>(ws + p->off_noise) + t; }
+    double *linv() const { return reinterpret_cast<double *>(ws + p->off_linv); }
     tlr_status load_dense() {
         dflag.assign((size_t)p->nt * p->nt, 0);
         TLR_HIP(hipMemcpyAsync(dflag.data(), ddense(), sizeof(int32_t) * dflag.size(), hipMemcpyDeviceToHost, s));
@@ -379,12 +381,17 @@ struct Ctx {
         return TLR_OK;
     }
     // The four status words of every job of a wave, with one copy of the
-    // tile range they span; valid after the next stream synchronisation.
+    // tile range they span, into pinned memory (so that both copies queue
+    // behind the wave's kernels without holding the host); valid after the
+    // next stream synchronisation and until the next read_stats.
     struct StatRead {
-        std::vector<int32_t> raw;
+        const int32_t *raw = nullptr;
         int64_t t0 = 0;
-        int32_t status = 0;  // the device status word, read in the same copy batch
+        const int32_t *status = nullptr;  // the device status word, read in the same copy batch
     };
+    int32_t *hstat = nullptr;  // pinned landing area of read_stats (pageable fallback below)
+    size_t hstat_cap = 0;
+    std::vector<int32_t> hstat_pageable;
     template <class JobT>
     tlr_status read_stats(const std::vector<JobT> &jobs, StatRead &sr) {
         if (jobs.empty()) return TLR_OK;
@@ -394,10 +401,22 @@ struct Ctx {
             lo = std::min(lo, t);
             hi = std::max(hi, t);
         }
+        if (!hstat) {
+            // every tile's words and the status word: enough for any wave
+            const size_t bytes = sizeof(int32_t) * (4 * (size_t)std::max<int64_t>(p->ntiles, 1) + 1);
+            hstat = reinterpret_cast<int32_t *>(pinned_pool().get(bytes, &hstat_cap));
+            if (!hstat) {
+                hstat_pageable.resize(bytes / sizeof(int32_t));
+                hstat = hstat_pageable.data();
+            }
+        }
+        const size_t words = (size_t)(hi - lo + 1) * 4;
         sr.t0 = lo;
-        sr.raw.assign((size_t)(hi - lo + 1) * 4, 0);
-        TLR_HIP(hipMemcpyAsync(sr.raw.data(), tstat(lo), sizeof(int32_t) * sr.raw.size(), hipMemcpyDeviceToHost, s));
-        TLR_HIP(hipMemcpyAsync(&sr.status, &params()->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        sr.raw = hstat;
+        sr.status = hstat + words;
+        TLR_HIP(hipMemcpyAsync(hstat, tstat(lo), sizeof(int32_t) * words, hipMemcpyDeviceToHost, s));
+        TLR_HIP(hipMemcpyAsync(hstat + words, &params()->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        in_flight = true;  // the copies land in pooled memory: wait before handing it back
         return TLR_OK;
     }
     tlr_status read_status(int *code) {
@@ -540,10 +559,19 @@ bool alloc_job(Ctx &c, Job &jb, int R) {
 }
 
 // out_t = op_t(in_t) (trans: op^T).  in_t == nullptr means the test matrix.
-tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega, bool into_z,
-                    const void *Yj, int Rj) {
-    const int nb = c.p->nb;
+// Staged first (descriptors in the descriptor area, host copies owned by
+// the StagedApply, which must stay where it is until launched), launched
+// later: staging every product and CholeskyQR of a range finder before its
+// second launch lets one upload carry all their descriptors.
+struct StagedApply {
     std::vector<GemmDesc> g1, g2, g3;  // factors and Schur panels share one element type
+    StagedGemm s1, s2, s3;
+};
+
+tlr_status stage_apply(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega, bool into_z, const void *Yj,
+                       int Rj, StagedApply &a) {
+    const int nb = c.p->nb;
+    std::vector<GemmDesc> &g1 = a.g1, &g2 = a.g2, &g3 = a.g3;
     const bool dense = jobs.front().A != nullptr;
     // Yj^T W is the same for every job of the column (W is one matrix, a job
     // of width k reads its first k columns): form it once, at the widest
@@ -574,14 +602,16 @@ tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega,
             g3.push_back(gd(big2, nb, F, std::max(Rj, 1), out, nb, nb, jb.k, Rj, -1.0, 1.0));
         }
     }
-    if (dense) return launch_gemms(c, trans, false, g1);
-    StagedGemm s1, s2, s3;
-    TLR_TRY(stage_gemms(c, true, false, g1, &s1, false, c.fa()));
-    TLR_TRY(stage_gemms(c, false, false, g2, &s2, false, c.fa()));
-    TLR_TRY(stage_gemms(c, false, false, g3, &s3, false, c.fa()));
-    TLR_TRY(launch_staged(c, s1));
-    TLR_TRY(launch_staged(c, s2));
-    return launch_staged(c, s3);
+    if (dense) return stage_gemms(c, trans, false, g1, &a.s1);
+    TLR_TRY(stage_gemms(c, true, false, g1, &a.s1, false, c.fa()));
+    TLR_TRY(stage_gemms(c, false, false, g2, &a.s2, false, c.fa()));
+    return stage_gemms(c, false, false, g3, &a.s3, false, c.fa());
+}
+
+tlr_status launch_apply(Ctx &c, const StagedApply &a) {
+    TLR_TRY(launch_staged(c, a.s1));
+    TLR_TRY(launch_staged(c, a.s2));
+    return launch_staged(c, a.s3);
 }
 
 // CholeskyQR of each job's panel (nb x k) in place, four passes: two with
@@ -595,20 +625,36 @@ tlr_status apply_op(Ctx &c, std::vector<Job> &jobs, bool trans, bool from_omega,
 // first basis of the range finder needs.  With `shifted` = 1 and passes = 3
 // (one shifted pass, two deflating ones) the directions above about 1e-11 of
 // the panel's norm come out orthonormal and the rest are deflated: enough when
-// the truncation threshold lies above that (see full_passes).
-tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int passes = 4, int shifted = 2) {
+// the truncation threshold lies above that (see full_passes).  Staged and
+// launched in two halves like the products above; staging moves each job's
+// Rt to where the launched passes leave it.
+struct StagedChol {
+    std::vector<GemmDesc> gram, a, b, d2;
+    std::vector<SmallDesc> sd;
+    const SmallDesc *dsd = nullptr;
+    StagedGemm sg, sa, sb, sc;
+    int passes = 0, shifted = 0, kmx = 0;
+    size_t nj = 0;
+    bool want_r = false;
+};
+
+tlr_status stage_cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int passes, int shifted,
+                        StagedChol &q) {
     const int nb = c.p->nb;
     const size_t nj = jobs.size();
-    int kmx = 0;
-    for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
+    q.passes = passes;
+    q.shifted = shifted;
+    q.nj = nj;
+    q.want_r = want_r;
+    q.kmx = 0;
+    for (auto &jb : jobs) q.kmx = std::max(q.kmx, jb.k);
     // every pass forms the Gram matrix of the same panel: one descriptor set;
     // the passes differ only in where R goes
-    std::vector<GemmDesc> gram;
-    std::vector<SmallDesc> sd((size_t)passes * nj);
-    for (size_t q = 0; q < nj; ++q) {
-        Job &jb = jobs[q];
+    q.sd.assign((size_t)passes * nj, SmallDesc{});
+    for (size_t t = 0; t < nj; ++t) {
+        Job &jb = jobs[t];
         double *Yp = on_z ? jb.Zb : jb.Yb;
-        gram.push_back(gd(Yp, nb, Yp, nb, jb.G, jb.k, jb.k, jb.k, nb, 1.0, 0.0));
+        q.gram.push_back(gd(Yp, nb, Yp, nb, jb.G, jb.k, jb.k, jb.k, nb, 1.0, 0.0));
         for (int it = 0; it < passes; ++it) {
             SmallDesc d{};
             d.A = jb.G;
@@ -622,49 +668,52 @@ tlr_status cholqr(Ctx &c, std::vector<Job> &jobs, bool on_z, bool want_r, int pa
             d.k = jb.k;
             d.tile_i = jb.i;
             d.tile_j = jb.j;
-            sd[(size_t)it * nj + q] = d;
+            q.sd[(size_t)it * nj + t] = d;
         }
     }
-    StagedGemm sg;
     // the Cholesky factorisation reads only the Gram matrix's lower triangle
-    TLR_TRY(stage_gemms(c, true, false, gram, &sg, true));
-    TLR_PUSH(dsd, c, sd);
-    StagedGemm sa, sb, sc;
-    std::vector<GemmDesc> a, b, d2;
+    TLR_TRY(stage_gemms(c, true, false, q.gram, &q.sg, true));
+    q.dsd = c.push(q.sd);
+    if (!q.dsd) return TLR_E_NOMEM;
     if (want_r && passes == 4) {
         // Rt = R4 R3 R2 R1, accumulated through T
         for (auto &jb : jobs) {
-            a.push_back(gd(jb.Rp[3], jb.k, jb.Rp[2], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
-            b.push_back(gd(jb.T, jb.k, jb.Rp[1], jb.k, jb.Rt, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
-            d2.push_back(gd(jb.Rt, jb.k, jb.Rp[0], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+            q.a.push_back(gd(jb.Rp[3], jb.k, jb.Rp[2], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+            q.b.push_back(gd(jb.T, jb.k, jb.Rp[1], jb.k, jb.Rt, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+            q.d2.push_back(gd(jb.Rt, jb.k, jb.Rp[0], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
         }
-        TLR_TRY(stage_gemms(c, false, false, a, &sa));
-        TLR_TRY(stage_gemms(c, false, false, b, &sb));
-        TLR_TRY(stage_gemms(c, false, false, d2, &sc));
+        TLR_TRY(stage_gemms(c, false, false, q.a, &q.sa));
+        TLR_TRY(stage_gemms(c, false, false, q.b, &q.sb));
+        TLR_TRY(stage_gemms(c, false, false, q.d2, &q.sc));
+        for (auto &jb : jobs) std::swap(jb.Rt, jb.T);  // the product ends in T
     } else if (want_r && passes == 3) {
         // Rt = R3 R2 R1 through T
         for (auto &jb : jobs) {
-            a.push_back(gd(jb.Rp[2], jb.k, jb.Rp[1], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
-            b.push_back(gd(jb.T, jb.k, jb.Rp[0], jb.k, jb.Rt, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+            q.a.push_back(gd(jb.Rp[2], jb.k, jb.Rp[1], jb.k, jb.T, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
+            q.b.push_back(gd(jb.T, jb.k, jb.Rp[0], jb.k, jb.Rt, jb.k, jb.k, jb.k, jb.k, 1.0, 0.0));
         }
-        TLR_TRY(stage_gemms(c, false, false, a, &sa));
-        TLR_TRY(stage_gemms(c, false, false, b, &sb));
+        TLR_TRY(stage_gemms(c, false, false, q.a, &q.sa));
+        TLR_TRY(stage_gemms(c, false, false, q.b, &q.sb));
     } else if (want_r) {
         return TLR_E_UNSUPPORTED;
     }
-    for (int it = 0; it < passes; ++it) {
-        const SmallDesc *dp = dsd + (size_t)it * nj;
-        const SmallDesc *hp = sd.data() + (size_t)it * nj;
-        TLR_TRY(launch_staged(c, sg));
-        TLR_LAUNCH(c, chol_small(dp, (int)nj, kmx, it < shifted ? 1 : 2, c.params(), c.s, hp));
-        TLR_LAUNCH(c, trsm_rows(dp, (int)nj, nb, kmx, c.s, hp));
+    return TLR_OK;
+}
+
+tlr_status launch_cholqr(Ctx &c, const StagedChol &q) {
+    const int nb = c.p->nb;
+    const size_t nj = q.nj;
+    for (int it = 0; it < q.passes; ++it) {
+        const SmallDesc *dp = q.dsd + (size_t)it * nj;
+        const SmallDesc *hp = q.sd.data() + (size_t)it * nj;
+        TLR_TRY(launch_staged(c, q.sg));
+        TLR_LAUNCH(c, chol_small(dp, (int)nj, q.kmx, it < q.shifted ? 1 : 2, c.params(), c.s, hp));
+        TLR_LAUNCH(c, trsm_rows(dp, (int)nj, nb, q.kmx, c.s, hp));
     }
-    if (want_r) {
-        TLR_TRY(launch_staged(c, sa));
-        TLR_TRY(launch_staged(c, sb));
-        TLR_TRY(launch_staged(c, sc));
-        if (passes == 4)
-            for (auto &jb : jobs) std::swap(jb.Rt, jb.T);
+    if (q.want_r) {
+        TLR_TRY(launch_staged(c, q.sa));
+        TLR_TRY(launch_staged(c, q.sb));
+        TLR_TRY(launch_staged(c, q.sc));
     }
     return TLR_OK;
 }
@@ -699,9 +748,9 @@ int full_passes(const tlr_plan_s *p, double sigma2, double tol) {
 
 constexpr int kQrSmallSketch = 64;  // widest sketch of the small register QRCP kernel
 
-// `after_first`: called once the first product of the range finder is
-// queued (the factorisation issues the diagonal tile's Cholesky on the second
-// stream there, ahead of this function's own use of that stream).
+// `after_first`: called once the first product of the range finder and its
+// basis are queued (the factorisation issues the diagonal tile's Cholesky on
+// the second stream there, ahead of this function's own use of that stream).
 tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int Rj, bool exact_svd,
                 int passes_q1, int passes_full, const std::function<tlr_status()> *after_first = nullptr) {
     if (jobs.empty()) return TLR_OK;
@@ -712,14 +761,27 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int 
     const int nb = c.p->nb;
     int kmx = 0;
     for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
-    TLR_TRY(apply_op(c, jobs, false, true, false, Yj, Rj));   // Yb = T W
+    // the first product and the first basis go out in one upload and at
+    // once; every later launch's descriptors are staged while they run and
+    // reach the device in a second upload
+    StagedApply a1, a2, a3;
+    StagedChol q1, q2, q3;
+    const int shifted_full = passes_full == 3 ? 1 : 2;
+    TLR_TRY(stage_apply(c, jobs, false, true, false, Yj, Rj, a1));   // Yb = T W
+    TLR_TRY(stage_cholqr(c, jobs, false, false, passes_q1, 2, q1));  // Yb = Q1 (only its span is used)
+    TLR_TRY(launch_apply(c, a1));
+    TLR_TRY(launch_cholqr(c, q1));
     if (after_first) TLR_TRY((*after_first)());
-    TLR_TRY(cholqr(c, jobs, false, false, passes_q1));       // Yb = Q1 (only its span is used)
-    TLR_TRY(apply_op(c, jobs, true, false, true, Yj, Rj));    // Zb = T^T Q1
-    TLR_TRY(cholqr(c, jobs, true, false, passes_full, passes_full == 3 ? 1 : 2));   // Zb = Q2
-    TLR_TRY(apply_op(c, jobs, false, false, false, Yj, Rj));  // Yb = T Q2
-    TLR_TRY(cholqr(c, jobs, false, true, passes_full, passes_full == 3 ? 1 : 2));   // Yb = Qw, Rt
-    if (!exact_svd) {
+    TLR_TRY(stage_apply(c, jobs, true, false, true, Yj, Rj, a2));              // Zb = T^T Q1
+    TLR_TRY(stage_cholqr(c, jobs, true, false, passes_full, shifted_full, q2));  // Zb = Q2
+    TLR_TRY(stage_apply(c, jobs, false, false, false, Yj, Rj, a3));            // Yb = T Q2
+    TLR_TRY(stage_cholqr(c, jobs, false, true, passes_full, shifted_full, q3));  // Yb = Qw, Rt
+    if (exact_svd) {
+        TLR_TRY(launch_apply(c, a2));
+        TLR_TRY(launch_cholqr(c, q2));
+        TLR_TRY(launch_apply(c, a3));
+        TLR_TRY(launch_cholqr(c, q3));
+    } else {
         std::vector<SmallDesc> sq;
         for (auto &jb : jobs) {
             SmallDesc d{};
@@ -746,20 +808,7 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int 
         // first, so the narrow ones form the tail of the list)
         size_t nw = 0;
         while (nw < sq.size() && sq[nw].k > kQrSmallSketch) ++nw;
-        if (nw > 0 && nw < sq.size()) {
-            TLR_PUSH(dsq, c, sq);
-            TLR_TRY(c.flush());
-            hipStream_t ss = c.fork();
-            TLR_TRY(qrcp_trunc(dsq + nw, (int)(sq.size() - nw), kQrSmallSketch, tol, c.p->min_tail, c.p->kmax,
-                               c.p->rcap, c.params(), ss));
-            TLR_TRY(qrcp_trunc(dsq, (int)nw, kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s,
-                               kQrSmallSketch + 1));
-            TLR_TRY(c.join());
-        } else {
-            TLR_PUSH(dsq, c, sq);
-            TLR_LAUNCH(c, qrcp_trunc(dsq, (int)sq.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(),
-                                     c.s));
-        }
+        TLR_PUSH(dsq, c, sq);
         std::vector<GemmDesc> gu2, gv2;
         for (auto &jb : jobs) {
             GemmDesc a = gd(jb.Yb, nb, jb.Xs, jb.k, jb.Uout, nb, nb, 0, jb.k, 1.0, 0.0);
@@ -769,8 +818,27 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int 
             v.N_dev = jb.stat;
             gv2.push_back(v);
         }
-        TLR_TRY(launch_gemms(c, false, false, gu2, c.fc()));
-        return launch_gemms(c, false, false, gv2, c.fc());
+        StagedGemm su, sv;
+        TLR_TRY(stage_gemms(c, false, false, gu2, &su, false, c.fc()));
+        TLR_TRY(stage_gemms(c, false, false, gv2, &sv, false, c.fc()));
+        TLR_TRY(launch_apply(c, a2));
+        TLR_TRY(launch_cholqr(c, q2));
+        TLR_TRY(launch_apply(c, a3));
+        TLR_TRY(launch_cholqr(c, q3));
+        if (nw > 0 && nw < sq.size()) {
+            TLR_TRY(c.flush());
+            hipStream_t ss = c.fork();
+            TLR_TRY(qrcp_trunc(dsq + nw, (int)(sq.size() - nw), kQrSmallSketch, tol, c.p->min_tail, c.p->kmax,
+                               c.p->rcap, c.params(), ss));
+            TLR_TRY(qrcp_trunc(dsq, (int)nw, kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(), c.s,
+                               kQrSmallSketch + 1));
+            TLR_TRY(c.join());
+        } else {
+            TLR_LAUNCH(c, qrcp_trunc(dsq, (int)sq.size(), kmx, tol, c.p->min_tail, c.p->kmax, c.p->rcap, c.params(),
+                                     c.s));
+        }
+        TLR_TRY(launch_staged(c, su));
+        return launch_staged(c, sv);
     }
     std::vector<SmallDesc> sd;
     for (auto &jb : jobs) {
@@ -914,6 +982,7 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->off_nrm_s = take(sizeof(double) * (size_t)p->nt * p->nt);
     p->off_nrm_l = take(sizeof(double) * (size_t)p->nt * p->nt);
     p->off_noise = take(sizeof(double) * (size_t)std::max<int64_t>(p->ntiles, 1));
+    p->off_linv = take(sizeof(double) * (size_t)nb * nb);  // L_jj^-1 of the current tile column
     p->dense_ok = (flags & TLR_PLAN_DENSE_TILES) != 0;
     p->svd_trunc = (flags & TLR_PLAN_SVD_TRUNCATION) != 0;
     p->off_dense = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
@@ -1213,7 +1282,6 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
     for (int i = 0; i < nt; ++i)
         for (int j = 0; j < i; ++j)
             if (r[(size_t)i * nt + j] < 0) return TLR_OK;  // overflow recorded by compress
-    std::vector<GemmDesc> hg((size_t)nt * 64 + 64);
     // a failure recorded on the device (a pivot lost, an arena overflow) is
     // seen at the next status read-back; the factorisation then stops
     bool failed = false;
@@ -1267,13 +1335,34 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
         // side stream is forked here, after the diagonal update; its launches
         // are issued once the main stream has the column's first batch of
         // work queued, so that their host-side cost does not starve it.
+        // After the factor, the same stream forms its inverse (L_jj X = I by
+        // the blocked substitution), which turns the triangular solves at the
+        // end of the column into one product.
         hipStream_t side_s = nullptr;
         const GemmDesc *dpd = nullptr;
+        const bool need_inv = j + 1 < nt;
+        const size_t nblk_inv = (size_t)cdiv(nb, 64);
+        SmallDesc inv_sd{};
+        const SmallDesc *dinv_sd = nullptr;
+        GemmDesc *dinv_g = nullptr;
+        double *const *dinv_id = nullptr;
         {
             std::vector<GemmDesc> pd((size_t)cdiv(nb, 64));
             potrf_tile_descs(c.diag(j), nb, pd.data());
             dpd = c.push(pd);
             if (!dpd) return TLR_E_NOMEM;
+            if (need_inv) {
+                inv_sd.Y = c.linv();
+                inv_sd.ldy = nb;
+                inv_sd.k = nb;
+                std::vector<GemmDesc> ig(nblk_inv);
+                trsm_left_lower_descs(c.diag(j), nb, &inv_sd, 1, ig.data(), false);
+                dinv_g = c.push(ig);
+                dinv_sd = c.push(&inv_sd, 1);
+                double *const idp[1] = {c.linv()};
+                dinv_id = c.push(idp, 1);
+                if (!dinv_g || !dinv_sd || !dinv_id) return TLR_E_NOMEM;
+            }
             TLR_TRY(c.flush());
             side_s = c.fork();
         }
@@ -1281,7 +1370,10 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
         const std::function<tlr_status()> issue_diag = [&]() -> tlr_status {
             if (diag_issued) return TLR_OK;
             diag_issued = true;
-            return potrf_tile(c.diag(j), nb, j, c.params(), dpd, side_s);
+            TLR_TRY(potrf_tile(c.diag(j), nb, j, c.params(), dpd, side_s));
+            if (!need_inv) return TLR_OK;
+            TLR_TRY(identity_batched(dinv_id, 1, nb, side_s));
+            return trsm_left_lower(c.diag(j), nb, dinv_sd, &inv_sd, 1, nb, dinv_g, nullptr, side_s, false);
         };
         // Schur complement of the tiles below, re-compressed once
         std::vector<int> rows;
@@ -1410,7 +1502,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                         TLR_TRY(c.sync_reset());
                     else
                         TLR_TRY(c.sync_main());
-                    if (!jobs.empty() && sr.status != 0) failed = true;
+                    if (!jobs.empty() && *sr.status != 0) failed = true;
                     std::vector<int32_t> st(4 * jobs.size());
                     for (size_t q = 0; q < jobs.size(); ++q)
                         std::memcpy(&st[4 * q], &sr.raw[(size_t)(tile_index(jobs[q].i, jobs[q].j) - sr.t0) * 4],
@@ -1468,30 +1560,46 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
         }
         TLR_TRY(issue_diag());
         if (failed) break;
-        // the triangular solves need the diagonal factor from the side stream
+        // the products below need the inverse from the side stream
         TLR_TRY(c.join());
-        // L_ij = U_ij (L_jj^-1 V_ij)^T
-        std::vector<SmallDesc> sd;
-        int maxc = 0;
-        for (int i : rows) {
-            const int rij = r[(size_t)i * nt + j];
-            if (rij <= 0) continue;
-            SmallDesc d{};
-            d.Y = static_cast<double *>(c.V(i, j));  // float32 data in a mixed plan (y32 below)
-            d.ldy = nb;
-            d.k = rij;
-            sd.push_back(d);
-            maxc = std::max(maxc, rij);
+        // L_ij = U_ij (L_jj^-1 V_ij)^T: T_i = L_jj^-1 V_ij into the arena (the
+        // inverse comes from the side stream), then back into the tile's slot;
+        // in groups that fit the arena, each group's copies queued before the
+        // next group's products overwrite the scratch
+        bool any_rank = false;
+        {
+            std::vector<GemmDesc> gi;
+            std::vector<CopyDesc> back;
+            int64_t mxw = 0;
+            const size_t mark = c.arena_used;
+            auto flush_group = [&]() -> tlr_status {
+                if (gi.empty()) return TLR_OK;
+                TLR_TRY(launch_gemms(c, false, false, gi, c.fb() | c.fc()));
+                TLR_PUSH(dbk, c, back);
+                TLR_LAUNCH(c, copy_batched(dbk, (int)back.size(), mxw, s));
+                gi.clear();
+                back.clear();
+                mxw = 0;
+                c.arena_used = mark;
+                return TLR_OK;
+            };
+            for (int i : rows) {
+                const int rij = r[(size_t)i * nt + j];
+                if (rij <= 0) continue;
+                any_rank = true;
+                void *Ti = c.alloc_fac((size_t)nb * rij);
+                if (!Ti) {
+                    TLR_TRY(flush_group());
+                    Ti = c.alloc_fac((size_t)nb * rij);
+                    if (!Ti) return TLR_E_NOMEM;
+                }
+                gi.push_back(gd(c.linv(), nb, c.V(i, j), nb, Ti, nb, nb, rij, nb, 1.0, 0.0));
+                back.push_back(CopyDesc{Ti, c.V(i, j), (int64_t)nb * rij, p->mixed ? 2 : 0});
+                mxw = std::max<int64_t>(mxw, (int64_t)nb * rij);
+            }
+            TLR_TRY(flush_group());
         }
-        if (!sd.empty()) {
-            TLR_PUSH(dsd, c, sd);
-            const size_t nblk = (size_t)cdiv(nb, 64);
-            if (hg.size() < sd.size() * nblk) hg.resize(sd.size() * nblk);
-            trsm_left_lower_descs(c.diag(j), nb, sd.data(), (int)sd.size(), hg.data(), p->mixed);
-            GemmDesc *dg = c.push(hg.data(), sd.size() * nblk);
-            if (!dg) return TLR_E_NOMEM;
-            TLR_LAUNCH(c, trsm_left_lower(c.diag(j), nb, dsd, sd.data(), (int)sd.size(), maxc, dg, nullptr, s,
-                                          p->mixed));
+        if (any_rank) {
             if (p->mixed) {
                 // ||L_ij||_F = ||L_jj^-1 V_ij||_F for the noise of later Schur complements
                 std::vector<NormDesc> nd;

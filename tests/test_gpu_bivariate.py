@@ -81,3 +81,31 @@ def test_bivariate_rejects_invalid():
     ws = plan.workspace()
     with pytest.raises(RuntimeError):
         plan.loglik_bivariate(ws, locs, to_dev(np.zeros(800)), (1.0, 1.0, 0.1, 0.5, 0.5, 1.2), 1e-9)
+
+
+@pytest.mark.parametrize("m,nb,theta,kind", [
+    (30, 300, (1.3, 0.7, 0.08, 0.5, 1.5, -0.6), "hilbert"),
+    (40, 400, (1.0, 2.0, 0.03, 0.5, 1.5, 0.95), "morton"),
+])
+def test_bivariate_mixed_precision(m, nb, theta, kind):
+    """A mixed plan (float32 factors) on the bivariate matrix: within the
+    mixed bound 1e-6 N of the dense oracle, no rank above the float64 plan's.
+    A mixed plan keeps no tile dense, so both plans take the rank cap nb."""
+    device()
+    tol = 1e-9
+    locs, z = problem(m, theta, kind, extra=2)
+    N = z.size
+    ref = BV.loglik(locs, z, theta)
+    outs = {}
+    for prec in ("fp64", "mixed_fp32"):
+        plan = B.Plan(N, nb, maxrank=nb, precision=prec)
+        ws = plan.workspace()
+        out = plan.loglik_bivariate(ws, to_dev(locs), to_dev(z), theta, tol).cpu().numpy()
+        outs[prec] = (out, plan.status(ws))
+    (o64, s64), (o32, s32) = outs["fp64"], outs["mixed_fp32"]
+    err = abs(o32[2] - ref.loglik)
+    print(f"bivariate mixed N={N} nb={nb}: mixed {o32[2]!r} fp64 {o64[2]!r} dense {ref.loglik!r} |dl|/N {err / N:.2e} "
+          f"rank sums {s32['rank_sum']} / {s64['rank_sum']}", flush=True)
+    assert s32["code"] == 0 and s64["code"] == 0
+    assert err <= 1e-6 * N
+    assert s32["rank_sum"] <= s64["rank_sum"]

@@ -107,3 +107,26 @@ def test_loglik_tgh_without_preimage_is_minus_infinity():
     ws = plan.workspace()
     out = plan.loglik_tgh(ws, to_dev(locs), to_dev(t), theta, tgh, 1e-9).cpu().numpy()
     assert out[2] == -np.inf
+
+
+def test_loglik_tgh_mixed_precision():
+    """The change of variables on a mixed plan: the Jacobian sum is the
+    float64 plan's to the bit (it reads only z), and l_TGH lies within the
+    mixed bound 1e-6 n of the oracle."""
+    device()
+    theta, tol, tgh = (1.0, 0.1, 0.5), 1e-9, (0.2, 2.0, 0.3, 0.15)
+    locs, t = tgh_problem(60, theta, tgh, extra=1)
+    n = locs.shape[0]
+    ref = OG.loglik_tgh(locs, t, theta, *tgh)
+    outs = {}
+    for prec in ("fp64", "mixed_fp32"):
+        plan = B.Plan(n, 360, precision=prec)
+        ws = plan.workspace()
+        outs[prec] = (plan.loglik_tgh(ws, to_dev(locs), to_dev(t), theta, tgh, tol).cpu().numpy(),
+                      plan.status(ws)["code"])
+    (o64, c64), (o32, c32) = outs["fp64"], outs["mixed_fp32"]
+    print(f"tgh mixed n={n}: mixed {o32[2]!r} fp64 {o64[2]!r} oracle {ref!r} |dl|/n {abs(o32[2] - ref) / n:.2e}",
+          flush=True)
+    assert c64 == 0 and c32 == 0
+    assert o32[3] == o64[3]
+    assert abs(o32[2] - ref) <= 1e-6 * n
