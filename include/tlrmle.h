@@ -430,6 +430,15 @@ tlr_status tlr_diag_peak_hbm(const void *d_src, void *d_dst, int64_t bytes, int3
 tlr_status tlr_diag_peak_mfma_f64(double *d_scratch, int64_t scratch_words, int32_t iters, double *h_tflops,
                                   void *stream);
 
+/* Host resources the library has created in this process and keeps in pools
+ * for reuse: *h_pinned pinned host staging buffers, *h_streams streams (side
+ * streams of the factorisation, batch worker streams).  Both counts stop
+ * growing once every pool has reached the size a workload needs, so a count
+ * that still grows across repeated evaluations would mean an allocation per
+ * evaluation.  The library makes no device allocation on the evaluation path
+ * (the workspace is the caller's).  TLR_E_INVAL for a null pointer. */
+tlr_status tlr_diag_alloc_counts(int64_t *h_pinned, int64_t *h_streams);
+
 /* Copy tile (i, j) of the matrix held in the workspace into d_out (nb x nb,
  * column-major): for i == j the dense diagonal tile (Sigma_jj after
  * tlr_gen_tiles, its Cholesky factor in the lower triangle after tlr_potrf);

@@ -91,6 +91,7 @@ _SIGNATURES = {
     "tlr_diag_gemm": (I32, [I32, I32, I32, I32, I32, F64, P, I32, P, I32, F64, P, I32, P]),
     "tlr_diag_svd": (I32, [I32, I32, P, F64, P, P, P, P, P]),
     "tlr_diag_peak_hbm": (I32, [P, P, I64, I32, ctypes.POINTER(F64), P]),
+    "tlr_diag_alloc_counts": (I32, [ctypes.POINTER(I64), ctypes.POINTER(I64)]),
     "tlr_diag_peak_mfma_f64": (I32, [P, I64, I32, ctypes.POINTER(F64), P]),
     "tlr_diag_gemm_strided": (I32, [I32, I32, I32, I32, I32, I32, F64, P, I32, I64, P, I32, I64, F64, P, I32, I64,
                                     P]),
@@ -374,6 +375,13 @@ def diag_gemm_strided(a, b, c, trans_a=False, trans_b=False, alpha=1.0, beta=0.0
                                        b.shape[1] * b.shape[2], float(beta), _ptr(c), M, M * N, _stream()),
            "tlr_diag_gemm_strided")
     return c
+
+
+def alloc_counts() -> tuple[int, int]:
+    """(pinned host buffers, streams) the library has created and pooled so far."""
+    a, b = I64(), I64()
+    _check(lib().tlr_diag_alloc_counts(ctypes.byref(a), ctypes.byref(b)), "tlr_diag_alloc_counts")
+    return a.value, b.value
 
 
 def peak_hbm(gib: float = 4.0, reps: int = 10, device="cuda") -> float:

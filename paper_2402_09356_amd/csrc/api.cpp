@@ -297,6 +297,12 @@ extern "C" tlr_status tlr_diag_peak_hbm(const void *d_src, void *d_dst, int64_t 
     return tlr::peak_hbm(d_src, d_dst, bytes, reps, h_gbs, as_stream(stream));
 }
 
+extern "C" tlr_status tlr_diag_alloc_counts(int64_t *h_pinned, int64_t *h_streams) {
+    if (!h_pinned || !h_streams) return TLR_E_INVAL;
+    tlr::alloc_counts(h_pinned, h_streams);
+    return TLR_OK;
+}
+
 extern "C" tlr_status tlr_diag_peak_mfma_f64(double *d_scratch, int64_t scratch_words, int32_t iters,
                                              double *h_tflops, void *stream) {
     return tlr::peak_mfma_f64(d_scratch, scratch_words, iters, h_tflops, as_stream(stream));

@@ -54,6 +54,7 @@ class StreamPool {
         while ((int)v.size() < count) {
             hipStream_t st = nullptr;
             if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return false;
+            note_stream_created();
             v.push_back(st);
         }
         out->assign(v.begin(), v.begin() + count);

@@ -92,6 +92,11 @@ struct CopyDesc {
     int32_t conv;  // 0: float64 -> float64, 1: float32 -> float64, 2: float32 -> float32
 };
 tlr_status copy_batched(const CopyDesc *d_descs, int count, int64_t max_words, hipStream_t s);
+// Host resources the library keeps in pools for the life of the process
+// (pinned staging buffers, streams), counted where they are created.
+void note_pinned_alloc();
+void note_stream_created();
+void alloc_counts(int64_t *pinned, int64_t *streams);
 // Each of the `count` nb x nb matrices (device pointer array) set to I.
 tlr_status identity_batched(double *const *d_ptrs, int count, int nb, hipStream_t s);
 // B_t <- L^-1 B_t for `count` right-hand-side panels (nb x cols_t, ld nb),

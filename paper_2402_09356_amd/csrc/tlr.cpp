@@ -20,6 +20,7 @@
 //             host as ranks become known (first fit at the fill mark; a
 //             recompressed tile reuses its slot when the new rank fits)
 #include <algorithm>
+#include <atomic>
 #include <functional>
 #include <climits>
 #include <cmath>
@@ -75,6 +76,8 @@ bool debug_enabled() {
 // copies), kept for the life of the process.  A buffer goes back to the pool
 // only after its stream has drained, so no copy from it is still in flight
 // when another context takes it.
+std::atomic<int64_t> g_pinned_allocs{0}, g_streams_created{0};
+
 class PinnedPool {
   public:
     char *get(size_t bytes, size_t *cap) {
@@ -94,6 +97,7 @@ class PinnedPool {
         }
         void *h = nullptr;
         if (hipHostMalloc(&h, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        note_pinned_alloc();
         *cap = bytes;
         return static_cast<char *>(h);
     }
@@ -133,6 +137,7 @@ class SidePool {
         SideStream n;
         n.dev = dev;
         if (hipStreamCreateWithFlags(&n.s, hipStreamNonBlocking) != hipSuccess) return false;
+        note_stream_created();
         if (hipEventCreateWithFlags(&n.from_main, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&n.from_side, hipEventDisableTiming) != hipSuccess) {
             (void)hipGetLastError();
@@ -748,9 +753,11 @@ int full_passes(const tlr_plan_s *p, double sigma2, double tol) {
 
 constexpr int kQrSmallSketch = 64;  // widest sketch of the small register QRCP kernel
 
-// `after_first`: called once the first product of the range finder and its
-// basis are queued (the factorisation issues the diagonal tile's Cholesky on
-// the second stream there, ahead of this function's own use of that stream).
+// `after_first`: called once the first two products of the range finder and
+// their bases are queued (the factorisation issues the diagonal tile's
+// Cholesky and inverse on the second stream there, ahead of this function's
+// own use of that stream, with enough work queued on the main stream to
+// cover the host's time for those launches).
 tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int Rj, bool exact_svd,
                 int passes_q1, int passes_full, const std::function<tlr_status()> *after_first = nullptr) {
     if (jobs.empty()) return TLR_OK;
@@ -761,28 +768,28 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int 
     const int nb = c.p->nb;
     int kmx = 0;
     for (auto &jb : jobs) kmx = std::max(kmx, jb.k);
-    // the first product and the first basis go out in one upload and at
-    // once; every later launch's descriptors are staged while they run and
-    // reach the device in a second upload
+    // every descriptor of the wave is staged first and reaches the device in
+    // one upload, ahead of the first launch: no copy waits in the stream
+    // between two steps of the chain
     StagedApply a1, a2, a3;
     StagedChol q1, q2, q3;
     const int shifted_full = passes_full == 3 ? 1 : 2;
-    TLR_TRY(stage_apply(c, jobs, false, true, false, Yj, Rj, a1));   // Yb = T W
-    TLR_TRY(stage_cholqr(c, jobs, false, false, passes_q1, 2, q1));  // Yb = Q1 (only its span is used)
-    TLR_TRY(launch_apply(c, a1));
-    TLR_TRY(launch_cholqr(c, q1));
-    if (after_first) TLR_TRY((*after_first)());
-    TLR_TRY(stage_apply(c, jobs, true, false, true, Yj, Rj, a2));              // Zb = T^T Q1
+    TLR_TRY(stage_apply(c, jobs, false, true, false, Yj, Rj, a1));              // Yb = T W
+    TLR_TRY(stage_cholqr(c, jobs, false, false, passes_q1, 2, q1));             // Yb = Q1 (only its span is used)
+    TLR_TRY(stage_apply(c, jobs, true, false, true, Yj, Rj, a2));               // Zb = T^T Q1
     TLR_TRY(stage_cholqr(c, jobs, true, false, passes_full, shifted_full, q2));  // Zb = Q2
-    TLR_TRY(stage_apply(c, jobs, false, false, false, Yj, Rj, a3));            // Yb = T Q2
+    TLR_TRY(stage_apply(c, jobs, false, false, false, Yj, Rj, a3));             // Yb = T Q2
     TLR_TRY(stage_cholqr(c, jobs, false, true, passes_full, shifted_full, q3));  // Yb = Qw, Rt
-    if (exact_svd) {
-        TLR_TRY(launch_apply(c, a2));
-        TLR_TRY(launch_cholqr(c, q2));
-        TLR_TRY(launch_apply(c, a3));
-        TLR_TRY(launch_cholqr(c, q3));
-    } else {
-        std::vector<SmallDesc> sq;
+    // truncation of Rt: sketches of up to 64 columns take the small register
+    // kernel, wider ones the larger kernels: when a wave has both, the narrow
+    // ones run on the second stream beside the wide ones (a wave is ordered
+    // widest first, so the narrow ones form the tail of the list)
+    std::vector<SmallDesc> sq;
+    std::vector<GemmDesc> gu2, gv2;
+    const SmallDesc *dsq = nullptr;
+    StagedGemm su, sv;
+    size_t nw = 0;
+    if (!exact_svd) {
         for (auto &jb : jobs) {
             SmallDesc d{};
             d.A = jb.Rt;
@@ -802,14 +809,9 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int 
             d.noise = jb.noise;
             sq.push_back(d);
         }
-        // sketches of up to 64 columns take the small register kernel, wider
-        // ones the larger kernels: when a wave has both, the narrow ones run
-        // on the second stream beside the wide ones (a wave is ordered widest
-        // first, so the narrow ones form the tail of the list)
-        size_t nw = 0;
         while (nw < sq.size() && sq[nw].k > kQrSmallSketch) ++nw;
-        TLR_PUSH(dsq, c, sq);
-        std::vector<GemmDesc> gu2, gv2;
+        dsq = c.push(sq);
+        if (!dsq) return TLR_E_NOMEM;
         for (auto &jb : jobs) {
             GemmDesc a = gd(jb.Yb, nb, jb.Xs, jb.k, jb.Uout, nb, nb, 0, jb.k, 1.0, 0.0);
             a.N_dev = jb.stat;
@@ -818,13 +820,17 @@ tlr_status rsvd(Ctx &c, std::vector<Job> &jobs, double tol, const void *Yj, int 
             v.N_dev = jb.stat;
             gv2.push_back(v);
         }
-        StagedGemm su, sv;
         TLR_TRY(stage_gemms(c, false, false, gu2, &su, false, c.fc()));
         TLR_TRY(stage_gemms(c, false, false, gv2, &sv, false, c.fc()));
-        TLR_TRY(launch_apply(c, a2));
-        TLR_TRY(launch_cholqr(c, q2));
-        TLR_TRY(launch_apply(c, a3));
-        TLR_TRY(launch_cholqr(c, q3));
+    }
+    TLR_TRY(launch_apply(c, a1));
+    TLR_TRY(launch_cholqr(c, q1));
+    TLR_TRY(launch_apply(c, a2));
+    TLR_TRY(launch_cholqr(c, q2));
+    if (after_first) TLR_TRY((*after_first)());
+    TLR_TRY(launch_apply(c, a3));
+    TLR_TRY(launch_cholqr(c, q3));
+    if (!exact_svd) {
         if (nw > 0 && nw < sq.size()) {
             TLR_TRY(c.flush());
             hipStream_t ss = c.fork();
@@ -936,6 +942,13 @@ int widen_k(const tlr_plan_s *p, int k, int kfull) {
 }
 
 }  // namespace
+
+void note_pinned_alloc() { g_pinned_allocs.fetch_add(1, std::memory_order_relaxed); }
+void note_stream_created() { g_streams_created.fetch_add(1, std::memory_order_relaxed); }
+void alloc_counts(int64_t *pinned, int64_t *streams) {
+    *pinned = g_pinned_allocs.load(std::memory_order_relaxed);
+    *streams = g_streams_created.load(std::memory_order_relaxed);
+}
 
 // ------------------------------------------------------------------ plan --
 

@@ -138,3 +138,11 @@ def test_mixed_precision_plan_rules():
     with pytest.raises(B.TlrError) as e:
         B.Plan(9000, 900, precision="mixed_fp32", truncation="svd")
     assert e.value.code == 3
+
+
+def test_alloc_counts_call():
+    """The pool counters read without a device; a null pointer is rejected."""
+    L = B.lib()
+    pinned, streams = B.alloc_counts()
+    assert pinned >= 0 and streams >= 0
+    assert L.tlr_diag_alloc_counts(None, None) == 1

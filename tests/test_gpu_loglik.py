@@ -340,9 +340,14 @@ def test_dense_tiles_random_order():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
 def test_evaluation_allocates_no_device_memory(precision):
-    """The workspace is the only device memory an evaluation uses: once the
-    library's streams and staging pools exist (first evaluation), further
-    evaluations leave the device's free memory unchanged."""
+    """The workspace is the only device memory an evaluation uses.  Once
+    the library's pooled streams and pinned staging buffers exist (one pass
+    over a sequence of evaluations), two more passes create none.  The
+    device's free memory over those passes moves by at most the HIP
+    runtime's own queue pools (kernel arguments, signals), which grow in
+    2 MiB steps with the depth of queued work, a few steps at most; a
+    device allocation of the library's (a workspace-sized buffer is
+    hundreds of MB here) would exceed that."""
     import gc
 
     dev = device()
@@ -353,19 +358,27 @@ def test_evaluation_allocates_no_device_memory(precision):
     ws = plan.workspace()
     dl, dz = to_dev(locs), to_dev(z)
     out = torch.empty(3, dtype=torch.float64, device=dev)
-    plan.loglik(ws, dl, dz, theta, tol, out=out)
+    seq = [theta, (1.2, 0.08, 0.5), (0.9, 0.12, 0.7)]
+    for th in seq:
+        plan.loglik(ws, dl, dz, th, tol, out=out)
     torch.cuda.synchronize()
     gc.collect()
     gc.disable()
     try:
+        counts_before = B.alloc_counts()
         free_before = torch.cuda.mem_get_info(dev)[0]
-        for th in [(1.2, 0.08, 0.5), (0.9, 0.12, 0.7)]:
-            plan.loglik(ws, dl, dz, th, tol, out=out)
+        for _ in range(2):
+            for th in seq:
+                plan.loglik(ws, dl, dz, th, tol, out=out)
         torch.cuda.synchronize()
         free_after = torch.cuda.mem_get_info(dev)[0]
+        counts_after = B.alloc_counts()
     finally:
         gc.enable()
-    assert free_after == free_before
+    print(f"{precision}: pooled (pinned, streams) {counts_before} -> {counts_after}; device bytes taken "
+          f"{free_before - free_after}", flush=True)
+    assert counts_after == counts_before
+    assert free_before - free_after <= 8 << 20
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
