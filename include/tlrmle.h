@@ -220,7 +220,10 @@ tlr_status tlr_compress(tlr_plan plan, double tol, void *d_ws, size_t ws_bytes, 
 /* TLR Cholesky factorisation Sigma~ = L L^T, in place in the workspace.
  * Left-looking by tile column: the Schur complement of each off-diagonal
  * tile is re-compressed once at the plan's tol; diagonal tiles are factored
- * densely in FP64.  A non-positive pivot sets TLR_NOT_SPD (tile k, k).
+ * densely in FP64, and each column's panel factors V_ij are multiplied by
+ * the explicit inverse of L_jj, formed beside the recompression on a second
+ * stream of default priority.  A non-positive pivot sets TLR_NOT_SPD (tile
+ * k, k).
  * Host-synchronises `stream` once per tile column (ranks are read back to
  * size the next column's work). */
 tlr_status tlr_potrf(tlr_plan plan, void *d_ws, size_t ws_bytes, void *stream);
