@@ -106,6 +106,16 @@ def test_splitmix64_vectorised_formulation_agrees():
     assert np.array_equal(O.splitmix64_stream(seed, count), z)
 
 
+def test_splitmix64_known_answers():
+    """Known-answer values of the generator's published C reference
+    implementation (Vigna's splitmix64.c), as used in other libraries' test
+    suites: the first five outputs from state 1234567, and the first output
+    from state 0 (0xE220A8397B1DCDAF)."""
+    assert [int(x) for x in O.splitmix64_stream(1234567, 5)] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431, 16408922859458223821]
+    assert int(O.splitmix64_stream(0, 1)[0]) == 0xE220A8397B1DCDAF
+
+
 def test_random_order_is_bijection_and_seeded():
     locs = synthetic.uniform_points(1000, 7)
     a = O.reorder(locs, "random", seed=11)
