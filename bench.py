@@ -101,7 +101,7 @@ def cpu_baseline(locs_ordered: np.ndarray, z_ordered: np.ndarray, theta, n_full:
 # MI355X published peaks used for roofline fractions
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6      # FP64 matrix (MFMA) and FP64 vector alike
-VALU_KERNELS = ("k_chol_small", "k_trsm_rows", "k_trsv_tile", "k_qrcp_trunc", "k_qrcp_reg", "k_jacobi_svd",
+VALU_KERNELS = ("k_chol_small", "k_trsm_rows", "k_qrcp_trunc", "k_qrcp_reg", "k_jacobi_svd",
                 "k_lr_gemv", "k_gen_tiles")
 
 

@@ -175,7 +175,8 @@ tlr_status tlr_plan_create(tlr_plan *out, int64_t n, int32_t nb, int32_t maxrank
 void tlr_plan_destroy(tlr_plan plan);
 
 /* Bytes of device workspace one evaluation needs: a fixed part (diagonal
- * tiles, sketch and small-matrix buffers, descriptors, tables, status word)
+ * tiles and their inverses, sketch and small-matrix buffers, descriptors,
+ * tables, status word)
  * and a factor arena that holds the low-rank factors U, V of every
  * off-diagonal tile in slots of 2 * nb * w entries (w >= the tile's rank;
  * 8-byte entries, 4-byte in a TLR_MIXED_FP32 plan).
@@ -222,14 +223,16 @@ tlr_status tlr_compress(tlr_plan plan, double tol, void *d_ws, size_t ws_bytes, 
  * tile is re-compressed once at the plan's tol; diagonal tiles are factored
  * densely in FP64, and each column's panel factors V_ij are multiplied by
  * the explicit inverse of L_jj, formed beside the recompression on a second
- * stream of default priority.  A non-positive pivot sets TLR_NOT_SPD (tile
- * k, k).
+ * stream of default priority and kept in the workspace for
+ * tlr_solve_logdet.  A non-positive pivot sets TLR_NOT_SPD (tile k, k).
  * Host-synchronises `stream` once per tile column (ranks are read back to
  * size the next column's work). */
 tlr_status tlr_potrf(tlr_plan plan, void *d_ws, size_t ws_bytes, void *stream);
 
 /* Forward solve y = L^-1 Z, log|Sigma~| = 2 sum log L_ii, quad = y^T y, in
- * FP64.  d_z: ordered observations, n float64.  d_out: out, 3 float64 on the
+ * FP64, after tlr_potrf on the same workspace (the diagonal blocks of the
+ * solve are products with the inverses it kept).  d_z: ordered observations,
+ * n float64.  d_out: out, 3 float64 on the
  * device: {logdet, quad, loglik}; loglik = -inf when the status is not OK. */
 tlr_status tlr_solve_logdet(tlr_plan plan, const double *d_z, void *d_ws, size_t ws_bytes,
                             double *d_out, void *stream);

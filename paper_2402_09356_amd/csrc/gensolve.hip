@@ -206,97 +206,45 @@ __global__ void k_pad_copy(const double *__restrict__ z, int64_t n, int64_t npad
     if (i < npad) out[i] = (i < n) ? z[i] : 0.0;
 }
 
-// Wave-uniform broadcast of lane l's double (two v_readlane).
-__device__ inline double readlane_d(double v, int l) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// y <- L^-1 y for one dense lower-triangular nb x nb tile (one work-group of
-// sixteen waves), 64 rows at a time: the diagonal block is staged in LDS and
-// solved by one wave (lane r holds y_r; the solved entry, y_r times the
-// reciprocal of the diagonal entry, is broadcast with readlane); then the rows
-// below take the block's columns.  The work-group is one compute unit reading
-// the whole lower triangle, so the update keeps as much of it in flight as
-// the registers allow: thread t takes column quarter t / 256 (16 columns) of
-// rows t % 256 + 256 k, eight columns at a time (32 loads in flight), and the
-// four quarters' partial sums meet in LDS in a fixed order.  The next
-// diagonal block is loaded during the update.
-constexpr int kTrsvThreads = 1024, kTrsvRowLanes = 256, kTrsvRowsPerLane = 4;
-
-__global__ __launch_bounds__(kTrsvThreads) void k_trsv_tile(const double *__restrict__ L, int nb,
-                                                            double *__restrict__ yv, const DevParams *params) {
-    __shared__ double Db[64 * 65];
-    __shared__ double xb[64];
-    __shared__ double part[4][kTrsvRowLanes * kTrsvRowsPerLane];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// y = L^-1 z for one diagonal tile, with L^-1 (lower triangular, nb x nb,
+// column-major) formed during the factorisation: a product, out of place.
+// A work-group owns 32 rows and splits the columns up to its last row 32
+// ways (thread g of a row takes c = g, g + 32, ...; four partial sums a
+// thread), then adds the 32 partials of each row in a fixed order, so the
+// result is the same on every call.  Columns past a row are exact zeros of
+// L^-1 and add nothing.
+constexpr int kTgRows = 32, kTgSplit = 32, kTgThreads = kTgRows * kTgSplit;
+__global__ __launch_bounds__(kTgThreads) void k_tri_gemv(const double *__restrict__ Li, int nb,
+                                                          const double *__restrict__ z, double *__restrict__ y,
+                                                          const DevParams *params) {
+    __shared__ double zs[4096];
+    __shared__ double part[kTgSplit][kTgRows];
     if (params->status != 0) return;
-    const int cq = tid / kTrsvRowLanes, rl = tid % kTrsvRowLanes;
-    // the diagonal block of b0: four entries a thread
-    double dv[4];
-    auto load_diag = [&](int b0) {
-        const int bs = (nb - b0 < 64) ? nb - b0 : 64;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + kTrsvThreads * u, r = e & 63, c = e >> 6;
-            dv[u] = (r < bs && c < bs && r >= c) ? L[(b0 + r) + (int64_t)(b0 + c) * nb] : 0.0;
+    const int r0 = blockIdx.x * kTgRows;
+    const int tid = threadIdx.x, rr = tid % kTgRows, g = tid / kTgRows;
+    const int r = r0 + rr;
+    const int cend = (nb < r0 + kTgRows) ? nb : r0 + kTgRows;
+    for (int c = tid; c < cend; c += kTgThreads) zs[c] = z[c];
+    __syncthreads();
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (r < nb) {
+        const double *__restrict__ row = Li + r;
+        int c = g;
+        for (; c + 3 * kTgSplit < cend; c += 4 * kTgSplit) {
+            a0 += row[(int64_t)c * nb] * zs[c];
+            a1 += row[(int64_t)(c + kTgSplit) * nb] * zs[c + kTgSplit];
+            a2 += row[(int64_t)(c + 2 * kTgSplit) * nb] * zs[c + 2 * kTgSplit];
+            a3 += row[(int64_t)(c + 3 * kTgSplit) * nb] * zs[c + 3 * kTgSplit];
         }
-    };
-    load_diag(0);
-    for (int b0 = 0; b0 < nb; b0 += 64) {
-        const int bs = (nb - b0 < 64) ? nb - b0 : 64;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + kTrsvThreads * u, r = e & 63, c = e >> 6;
-            Db[r + 65 * c] = dv[u];
-        }
-        __syncthreads();
-        if (wave == 0) {
-            double v = (lane < bs) ? yv[b0 + lane] : 0.0;
-            // the reciprocals of the diagonal, all at once, keep the divide
-            // off the dependent chain of the substitution
-            const double ivl = (lane < bs) ? 1.0 / Db[lane * 66] : 0.0;
-            for (int r = 0; r < bs; ++r) {
-                const double xr = readlane_d(v, r) * readlane_d(ivl, r);
-                const double lr = Db[lane + 65 * r];
-                v = (lane == r) ? xr : ((lane > r) ? v - lr * xr : v);
-            }
-            xb[lane] = (lane < bs) ? v : 0.0;  // zero past the block: the row update reads all 64
-            if (lane < bs) yv[b0 + lane] = v;
-        }
-        __syncthreads();
-        if (b0 + 64 < nb) load_diag(b0 + 64);  // in flight during the update below
-        // rows below the block, in chunks of 1024 rows
-        for (int base = b0 + bs; base < nb; base += kTrsvRowLanes * kTrsvRowsPerLane) {
-            double acc[kTrsvRowsPerLane] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-            for (int h = 0; h < 2; ++h) {
-                const int c0 = 16 * cq + 8 * h;
-                double lv[kTrsvRowsPerLane][8];
-#pragma unroll
-                for (int k = 0; k < kTrsvRowsPerLane; ++k)
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int row = base + rl + kTrsvRowLanes * k;
-                        lv[k][u] = (row < nb && c0 + u < bs) ? L[row + (int64_t)(b0 + c0 + u) * nb] : 0.0;
-                    }
-#pragma unroll
-                for (int k = 0; k < kTrsvRowsPerLane; ++k)
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) acc[k] += lv[k][u] * xb[c0 + u];
-            }
-#pragma unroll
-            for (int k = 0; k < kTrsvRowsPerLane; ++k) part[cq][rl + kTrsvRowLanes * k] = acc[k];
-            __syncthreads();
-            {
-                const int row = base + tid;
-                if (tid < kTrsvRowLanes * kTrsvRowsPerLane && row < nb)
-                    yv[row] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
-            }
-            __syncthreads();
-        }
+        for (; c < cend; c += kTgSplit) a0 += row[(int64_t)c * nb] * zs[c];
+    }
+    part[g][rr] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (g == 0 && r < nb) {
+        double acc = part[0][rr];
+#pragma unroll 8
+        for (int q = 1; q < kTgSplit; ++q) acc += part[q][rr];
+        y[r] = acc;
     }
 }
 
@@ -507,11 +455,12 @@ tlr_status identity_batched(double *const *d_ptrs, int count, int nb, hipStream_
     return TLR_OK;
 }
 
-tlr_status trsv_tile(const double *L, int nb, double *yv, const DevParams *params, hipStream_t s) {
-    static const int cls = ktimer_class("k_trsv_tile");
+tlr_status tri_gemv(const double *Li, int nb, const double *z, double *y, const DevParams *params, hipStream_t s) {
+    if (nb > 4096) return TLR_E_UNSUPPORTED;
+    static const int cls = ktimer_class("k_tri_gemv");
     const double b = nb;
-    KTimer kt(cls, s, b * b, 8.0 * (b * (b + 1.0) / 2.0 + 2.0 * b), true);
-    hipLaunchKernelGGL(k_trsv_tile, dim3(1), dim3(kTrsvThreads), 0, s, L, nb, yv, params);
+    KTimer kt(cls, s, b * (b + 1.0), 8.0 * (b * (b + 1.0) / 2.0 + 2.0 * b), true);
+    hipLaunchKernelGGL(k_tri_gemv, dim3((unsigned)cdiv(nb, kTgRows)), dim3(kTgThreads), 0, s, Li, nb, z, y, params);
     TLR_HIP(hipGetLastError());
     return TLR_OK;
 }

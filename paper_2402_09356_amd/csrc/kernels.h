@@ -133,7 +133,9 @@ tlr_status gen_tiles_biv_launch(const GenDesc *d_descs, int count, int nb, int64
 tlr_status gaussian_fill(double *out, int64_t count, uint64_t seed, hipStream_t s);
 tlr_status split_locs(const double *locs, int64_t n, int64_t npad, double *x, double *y, hipStream_t s);
 tlr_status pad_copy(const double *z, int64_t n, int64_t npad, double *out, hipStream_t s);
-tlr_status trsv_tile(const double *L, int nb, double *yv, const DevParams *params, hipStream_t s);
+// y = Li z for one nb x nb lower-triangular inverse Li (column-major), out of
+// place; skipped once the status word records a failure.
+tlr_status tri_gemv(const double *Li, int nb, const double *z, double *y, const DevParams *params, hipStream_t s);
 size_t gemv_desc_bytes();
 void make_gemv_desc(void *dst, const void *U, const void *V, const double *yj, double *yi,
                     const int32_t *r_dev);

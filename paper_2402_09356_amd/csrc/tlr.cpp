@@ -39,7 +39,7 @@ struct tlr_plan_s {
     tlr_precision prec;
     uint32_t flags;
     size_t off_params, off_x, off_y, off_diag, off_rsig, off_rL, off_tstat, off_tofs, off_yvec, off_omega,
-        off_desc, off_arena, off_knu, off_dense, off_wide, off_nrm_s, off_nrm_l, off_noise, off_linv, off_fac;
+        off_desc, off_arena, off_knu, off_dense, off_wide, off_nrm_s, off_nrm_l, off_noise, off_linv, off_ysol, off_fac;
     bool mixed;  // TLR_MIXED_FP32: low-rank factors stored in float32
     int fw;      // bytes per stored factor entry (8, or 4 when mixed)
     bool dense_ok;   // TLR_PLAN_DENSE_TILES: over-rank tiles kept dense in the wide slots
@@ -315,7 +315,8 @@ struct Ctx {
     double *nrm_s() const { return reinterpret_cast<double *>(ws + p->off_nrm_s); }
     double *nrm_l() const { return reinterpret_cast<double *>(ws + p->off_nrm_l); }
     double *noise(int64_t t) const { return reinterpret_cast<double *>(ws + p->off_noise) + t; }
-    double *linv() const { return reinterpret_cast<double *>(ws + p->off_linv); }
+    double *linv(int j) const { return reinterpret_cast<double *>(ws + p->off_linv) + (int64_t)j * p->nb * p->nb; }
+    double *ysol() const { return reinterpret_cast<double *>(ws + p->off_ysol); }
     tlr_status load_dense() {
         dflag.assign((size_t)p->nt * p->nt, 0);
         TLR_HIP(hipMemcpyAsync(dflag.data(), ddense(), sizeof(int32_t) * dflag.size(), hipMemcpyDeviceToHost, s));
@@ -995,12 +996,13 @@ tlr_status plan_create(tlr_plan *out, int64_t n, int nb, int maxrank, tlr_precis
     p->off_nrm_s = take(sizeof(double) * (size_t)p->nt * p->nt);
     p->off_nrm_l = take(sizeof(double) * (size_t)p->nt * p->nt);
     p->off_noise = take(sizeof(double) * (size_t)std::max<int64_t>(p->ntiles, 1));
-    p->off_linv = take(sizeof(double) * (size_t)nb * nb);  // L_jj^-1 of the current tile column
+    p->off_linv = take(sizeof(double) * (size_t)p->nt * nb * nb);  // L_jj^-1 of every tile column
     p->dense_ok = (flags & TLR_PLAN_DENSE_TILES) != 0;
     p->svd_trunc = (flags & TLR_PLAN_SVD_TRUNCATION) != 0;
     p->off_dense = take(sizeof(int32_t) * (size_t)p->nt * p->nt);
     p->off_wide = p->dense_ok ? take(sizeof(double) * 2 * (size_t)nb * nb * (size_t)std::max<int64_t>(p->ntiles, 1)) : 0;
     p->off_yvec = take(sizeof(double) * p->npad);
+    p->off_ysol = take(sizeof(double) * p->npad);
     p->off_omega = take(sizeof(double) * (size_t)nb * p->kmax);
     p->off_knu = take(sizeof(double) * 3 * kChebPieces * (kChebDeg + 1));  // three for the bivariate model
     // descriptors of one wave: about 42 (GEMM and small-kernel descriptors,
@@ -1350,11 +1352,10 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
         // work queued, so that their host-side cost does not starve it.
         // After the factor, the same stream forms its inverse (L_jj X = I by
         // the blocked substitution), which turns the triangular solves at the
-        // end of the column into one product.
+        // end of the column into one product; the forward solve of the
+        // likelihood uses it again.
         hipStream_t side_s = nullptr;
         const GemmDesc *dpd = nullptr;
-        const bool need_inv = j + 1 < nt;
-        const size_t nblk_inv = (size_t)cdiv(nb, 64);
         SmallDesc inv_sd{};
         const SmallDesc *dinv_sd = nullptr;
         GemmDesc *dinv_g = nullptr;
@@ -1364,18 +1365,16 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             potrf_tile_descs(c.diag(j), nb, pd.data());
             dpd = c.push(pd);
             if (!dpd) return TLR_E_NOMEM;
-            if (need_inv) {
-                inv_sd.Y = c.linv();
-                inv_sd.ldy = nb;
-                inv_sd.k = nb;
-                std::vector<GemmDesc> ig(nblk_inv);
-                trsm_left_lower_descs(c.diag(j), nb, &inv_sd, 1, ig.data(), false);
-                dinv_g = c.push(ig);
-                dinv_sd = c.push(&inv_sd, 1);
-                double *const idp[1] = {c.linv()};
-                dinv_id = c.push(idp, 1);
-                if (!dinv_g || !dinv_sd || !dinv_id) return TLR_E_NOMEM;
-            }
+            inv_sd.Y = c.linv(j);
+            inv_sd.ldy = nb;
+            inv_sd.k = nb;
+            std::vector<GemmDesc> ig((size_t)cdiv(nb, 64));
+            trsm_left_lower_descs(c.diag(j), nb, &inv_sd, 1, ig.data(), false);
+            dinv_g = c.push(ig);
+            dinv_sd = c.push(&inv_sd, 1);
+            double *const idp[1] = {c.linv(j)};
+            dinv_id = c.push(idp, 1);
+            if (!dinv_g || !dinv_sd || !dinv_id) return TLR_E_NOMEM;
             TLR_TRY(c.flush());
             side_s = c.fork();
         }
@@ -1384,7 +1383,6 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
             if (diag_issued) return TLR_OK;
             diag_issued = true;
             TLR_TRY(potrf_tile(c.diag(j), nb, j, c.params(), dpd, side_s));
-            if (!need_inv) return TLR_OK;
             TLR_TRY(identity_batched(dinv_id, 1, nb, side_s));
             return trsm_left_lower(c.diag(j), nb, dinv_sd, &inv_sd, 1, nb, dinv_g, nullptr, side_s, false);
         };
@@ -1606,7 +1604,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                     Ti = c.alloc_fac((size_t)nb * rij);
                     if (!Ti) return TLR_E_NOMEM;
                 }
-                gi.push_back(gd(c.linv(), nb, c.V(i, j), nb, Ti, nb, nb, rij, nb, 1.0, 0.0));
+                gi.push_back(gd(c.linv(j), nb, c.V(i, j), nb, Ti, nb, nb, rij, nb, 1.0, 0.0));
                 back.push_back(CopyDesc{Ti, c.V(i, j), (int64_t)nb * rij, p->mixed ? 2 : 0});
                 mxw = std::max<int64_t>(mxw, (int64_t)nb * rij);
             }
@@ -1654,7 +1652,7 @@ tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_byt
     for (int j = 0; j < nt; ++j) {
         first[j] = (int)cnt;
         for (int i = j + 1; i < nt; ++i) {
-            make_gemv_desc(hv.data() + gb * cnt, c.U(i, j), c.V(i, j), c.yvec() + (int64_t)j * nb,
+            make_gemv_desc(hv.data() + gb * cnt, c.U(i, j), c.V(i, j), c.ysol() + (int64_t)j * nb,
                            c.yvec() + (int64_t)i * nb, c.rL() + (size_t)i * nt + j);
             ++cnt;
         }
@@ -1666,11 +1664,13 @@ tlr_status solve_logdet(tlr_plan p, const double *d_z, void *d_ws, size_t ws_byt
         if (!dv) return TLR_E_NOMEM;
     }
     for (int j = 0; j < nt; ++j) {
-        TLR_TRY(trsv_tile(c.diag(j), nb, c.yvec() + (int64_t)j * nb, c.params(), s));
+        // y_j = L_jj^-1 z_j (the inverse kept by the factorisation); then
+        // z_i -= L_ij y_j below
+        TLR_TRY(tri_gemv(c.linv(j), nb, c.yvec() + (int64_t)j * nb, c.ysol() + (int64_t)j * nb, c.params(), s));
         const int count = first[j + 1] - first[j];
         if (count > 0) TLR_LAUNCH(c, lr_gemv(dv + gb * first[j], count, nb, c.params(), s, p->mixed));
     }
-    TLR_TRY(logdet_quad(c.diag(0), nb, nt, p->n, c.yvec(), c.params(), d_out, s));
+    TLR_TRY(logdet_quad(c.diag(0), nb, nt, p->n, c.ysol(), c.params(), d_out, s));
     TLR_HIP(hipStreamSynchronize(s));
     return TLR_OK;
 }
