@@ -177,8 +177,10 @@ struct Ctx {
     size_t desc_used = 0;
     size_t flushed = 0;             // staged descriptor bytes already on the device
     size_t arena_used = 0;
+    size_t arena_off = 0, arena_cap = 0;  // the scratch arena in use (the plan's, or a larger one)
 
-    Ctx(const tlr_plan_s *plan, void *w, hipStream_t st) : p(plan), ws(static_cast<char *>(w)), s(st) {
+    Ctx(const tlr_plan_s *plan, void *w, hipStream_t st)
+        : p(plan), ws(static_cast<char *>(w)), s(st), arena_off(plan->off_arena), arena_cap(plan->arena_bytes) {
         hdesc = pinned_pool().get(plan->desc_bytes, &hdesc_cap);
         if (!hdesc) {
             hdesc_pageable.resize(plan->desc_bytes);
@@ -277,6 +279,25 @@ struct Ctx {
         fac_fill += need;
         return true;
     }
+    // Scratch for a compression wave: the plan's arena, or the free tail of
+    // the factor arena when that is larger (a workspace sized for maxrank
+    // slots holds far more than the factors need).  A wave's new slots must
+    // stay below the tail taken: a job's scratch holds at least the nb x nb
+    // tile and four nb x k panels (8 (nb^2 + 4 nb k) bytes), its slot at most
+    // 2 nb k entries of 8 bytes, so the slots of a wave need at most
+    // rho = 2 k / (nb + 4 k) of its scratch, k <= kmax; a share
+    // 1 / (1 + rho) of the free space (less 2%) leaves them room.
+    void use_free_tail() {
+        arena_off = p->off_arena;
+        arena_cap = p->arena_bytes;
+        const size_t fill_end = p->off_fac + (size_t)fac_fill * p->fw;
+        if (ws_size <= fill_end + 4096) return;
+        const double rho = 2.0 * p->kmax / ((double)p->nb + 4.0 * p->kmax);
+        const size_t tail = (size_t)((double)(ws_size - fill_end) * 0.98 / (1.0 + rho)) & ~(size_t)255;
+        if (tail <= arena_cap) return;
+        arena_off = (ws_size - tail) & ~(size_t)255;
+        arena_cap = tail;
+    }
     void reset_slots() {
         slots.assign((size_t)std::max<int64_t>(p->ntiles, 1), Slot{0, 0, 0});
         fac_fill = 0;
@@ -363,8 +384,8 @@ struct Ctx {
     }
     double *alloc(size_t words) {
         const size_t bytes = align_up(std::max<size_t>(words, 1) * sizeof(double), 256);
-        if (arena_used + bytes > p->arena_bytes) return nullptr;
-        double *d = reinterpret_cast<double *>(ws + p->off_arena + arena_used);
+        if (arena_used + bytes > arena_cap) return nullptr;
+        double *d = reinterpret_cast<double *>(ws + arena_off + arena_used);
         arena_used += bytes;
         return d;
     }
@@ -1164,12 +1185,13 @@ tlr_status compress(tlr_plan p, double tol, void *d_ws, size_t ws_bytes, int32_t
         size_t pos = 0;
         while (pos < pending.size() && !arena_full) {
             c.arena_used = 0;
+            c.use_free_tail();
             std::vector<Job> jobs;
             std::vector<GenDesc> gens;
             while (pos < pending.size()) {
                 const Pending &pt = pending[pos];
                 const size_t need = job_words(nb, pt.k, 0, 0, true) * sizeof(double);
-                if (c.arena_used + need > p->arena_bytes && !jobs.empty()) break;
+                if (c.arena_used + need > c.arena_cap && !jobs.empty()) break;
                 Job jb{};
                 jb.i = pt.i;
                 jb.j = pt.j;
@@ -1416,7 +1438,7 @@ tlr_status potrf(tlr_plan p, void *d_ws, size_t ws_bytes, hipStream_t s) {
                             words += (size_t)nb * nb + 64;
                         else
                             words += job_words(nb, kk[i], rij, Rj, false) + (p->dense_ok ? (size_t)nb * nb + 256 : 0);
-                        if (c.arena_used + words * sizeof(double) > p->arena_bytes && !(jobs.empty() && djobs.empty()))
+                        if (c.arena_used + words * sizeof(double) > c.arena_cap && !(jobs.empty() && djobs.empty()))
                             break;
                         Job jb{};
                         jb.i = i;
