@@ -279,6 +279,9 @@ def main():
                          "abs_dl_per_n": dl / n, "abs_dlogdet": abs(float(got[0]) - v["logdet"]), "ms": dt_ms})
         print(f"# accuracy theta={v['theta']}: gpu {got[2]!r} oracle {v['loglik']!r} |dl|={dl:.3e}",
               file=sys.stderr, flush=True)
+    # rank tables of the last stored theta's evaluation (read before the
+    # concurrency run below evaluates other thetas on this workspace)
+    st = plan.status(ws)
     bound_per_n = 1e-8 if args.precision == "fp64" else 1e-6
     accuracy = {"values": acc_vals, "max_abs_dl": max(a["abs_dl"] for a in acc_vals),
                 "bound_per_n": bound_per_n,
@@ -339,7 +342,6 @@ def main():
     for k in stats[:3]:
         print(f"# timed {k['name']:20s} launches {k['launches']:7d}  total {k['total_ms']:10.2f} ms  "
               f"avg {1e3 * k['total_ms'] / max(k['launches'], 1):9.2f} us", file=sys.stderr)
-    st = plan.status(ws)
     lat_ms = np.asarray(lat) * 1e3
     workload = (f"{args.config}: n={n} jittered grid, nu=0.5 beta=0.1 sigma2=1, {kind} order, nb={nb}, "
                 f"tol={tol:g}, theta=theta_true*exp(0.2 N(0,I)) per step, {args.precision}")
