@@ -589,7 +589,7 @@ bool alloc_job(Ctx &c, Job &jb, int R) {
 // Staged first (descriptors in the descriptor area, host copies owned by
 // the StagedApply, which must stay where it is until launched), launched
 // later: staging every product and CholeskyQR of a range finder before its
-// second launch lets one upload carry all their descriptors.
+// first launch lets one upload carry all their descriptors.
 struct StagedApply {
     std::vector<GemmDesc> g1, g2, g3;  // factors and Schur panels share one element type
     StagedGemm s1, s2, s3;
